@@ -1,0 +1,240 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) HLBM mean-flow adjoint library.
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the method
+ * of Ito et al., "Mean-Flow Adjoint Sensitivity Analysis of Unsteady Flow
+ * Around Porous Cylinders Using a Homogenized Lattice Boltzmann Method":
+ *
+ *   primal HLBM sweep (Sec. 2, Eq. hlbm; optional Smagorinsky closure,
+ *   Eqs. sgsStress/turbVisc/tauEff)  ->  FP64 tracking average of the flow
+ *   (Sec. 3.3, Eq. averageObjective)  ->  adjoint LBM sweep on the frozen
+ *   (mean) flow (Sec. 3.2-3.3, Eqs. adjoint_steady/adjoint_unsteady)  ->
+ *   gradient assembly dJ/dd over the porosity field (Eqs. gradients_steady/
+ *   gradients_unsteady), for the drag (J_FFA, Eq. obj_ffa) and dissipation
+ *   (J_DISS, Eq. obj_diss) objectives (Sec. 4).
+ *
+ * The call sequence follows the paper's problem statement (Sec. 3.1: minimise
+ * J(alpha, f) subject to the lattice Boltzmann residual G(alpha, f) = 0, and
+ * return dJ/dalpha) and the three phases of its Algorithm 1 (primal, adjoint,
+ * gradient assembly).  The control variable is the lattice porosity d of
+ * Sec. 2.1 (d = 1 fluid, d = 0 solid; d = 1 - dx^2 tau nu / K).
+ *
+ * Conventions
+ *  - Lattice units: dx = dt = 1, c_s^2 = 1/3.  Cell index
+ *    cell = x + nx*(y + ny*z).  Population arrays exchanged through this ABI
+ *    use the canonical layout value[i*n + cell] with the direction order
+ *      D2Q9 : 0 rest; 1..4 = (1,0),(0,1),(1,1),(-1,1); 5..8 their negatives
+ *      D3Q19: 0 rest; 1..9 = (1,0,0),(0,1,0),(0,0,1),(1,1,0),(1,-1,0),
+ *             (1,0,1),(1,0,-1),(0,1,1),(0,1,-1); 10..18 their negatives.
+ *  - Every call returns hlbm_status (0 = HLBM_OK).  On error nothing is
+ *    enqueued; hlbm_last_error() gives a thread-local message.
+ *  - Ownership: the caller owns every buffer it passes; set_* calls copy,
+ *    get_* calls write into caller memory.  The handle owns all device memory
+ *    it allocates until hlbm_destroy.
+ *  - Memory kind: arguments typed `const double*`/`double*` with an
+ *    `hlbm_mem` flag are host pointers (HLBM_MEM_HOST) or device pointers on
+ *    the lattice's device (HLBM_MEM_DEVICE), e.g. a PyTorch tensor's
+ *    data_ptr().  All exchanged values are FP64 whatever the precision form.
+ *  - Streams: every kernel is enqueued on desc.stream (a hipStream_t; NULL is
+ *    the null stream).  Calls that return values to the host synchronise that
+ *    stream; all others are asynchronous.
+ *  - Threads: one host thread per handle at a time; different handles may be
+ *    used from different threads.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hlbm_lattice_s* hlbm_lattice;
+
+typedef enum {
+  HLBM_OK = 0,
+  HLBM_W_NOT_CONVERGED = 1, /* iteration limit reached; outputs valid */
+  HLBM_E_INVALID = -1,      /* bad argument (size, range, NaN, null) */
+  HLBM_E_OOM = -2,          /* device allocation failed */
+  HLBM_E_STATE = -3,        /* call order violated (e.g. adjoint before objective) */
+  HLBM_E_DIVERGED = -4,     /* non-finite state or residual; outputs undefined */
+  HLBM_E_DEVICE = -5        /* HIP runtime error */
+} hlbm_status;
+
+typedef enum { HLBM_D2Q9 = 0, HLBM_D3Q19 = 1 } hlbm_stencil;
+
+/* Precision forms.  FP64: FP64 storage and arithmetic.  FP32: FP32 storage
+ * and arithmetic.  FP16S: FP32 arithmetic, populations stored as binary16
+ * values of f_i - w_i.  In every form the window accumulators, objective and
+ * gradient reductions and the adjoint residual are FP64. */
+typedef enum { HLBM_FP64 = 0, HLBM_FP32 = 1, HLBM_FP16S = 2 } hlbm_precision;
+
+/* Boundary kinds per axis.  WALLS: halfway bounce-back at -1/2 and n-1/2.
+ * INLET_OUTLET (x only): column x = 0 is an equilibrium velocity inlet
+ * f = f^eq(1, u_in(y)) (not collided); column x = nx-1 is a pressure outlet
+ * whose missing populations come from a virtual column holding
+ * f^eq(1, u of the last column) (density 1 as the paper's p_out = 0, zero-
+ * gradient velocity).  Walls take precedence at corners. */
+typedef enum { HLBM_BC_PERIODIC = 0, HLBM_BC_WALLS = 1, HLBM_BC_INLET_OUTLET = 2 } hlbm_bc;
+typedef enum { HLBM_INLET_UNIFORM = 1, HLBM_INLET_PARABOLIC = 2 } hlbm_inlet;
+
+/* Objectives (Sec. 4).  FFA: far-field drag over a plane, Eq. obj_ffa, with
+ * p = rho/3.  DISS: viscous + porous dissipation over a box, Eq. obj_diss,
+ * S = -Pi/(2 tau0 c_s^2) from the non-equilibrium part with respect to
+ * f^eq(rho, u), nu/K = (1 - d)/tau0.  MOMENTUM: sum of j_x (test objective). */
+typedef enum { HLBM_OBJ_FFA = 0, HLBM_OBJ_DISS = 1, HLBM_OBJ_MOMENTUM = 2 } hlbm_objective;
+
+/* Treatment of the Smagorinsky closure in the adjoint (Sec. 5.4).  FROZEN:
+ * frozen-turbulence assumption, relaxation time tau_adj + (mean tau_eff -
+ * tau0) held constant.  DIFFERENTIATED: tau_eff(fbar) with tau0 -> tau_adj and
+ * the extra (1/tau_eff)^2 dtau_eff/df f^neq term (needs the window to track
+ * mean populations, desc.track_mean_populations = 1). */
+typedef enum { HLBM_TURB_FROZEN = 0, HLBM_TURB_DIFFERENTIATED = 1 } hlbm_turb;
+
+/* Adjoint source.  STEADY: Jacobians and dJ/df at the current primal state
+ * (Eq. adjoint_steady).  MEAN: Jacobians at the window-mean state and the
+ * window mean of dJ/df, dJ/dd (Eqs. adjoint_unsteady, gradients_unsteady). */
+typedef enum { HLBM_SOURCE_STEADY = 0, HLBM_SOURCE_MEAN = 1 } hlbm_source;
+
+typedef enum { HLBM_MEM_HOST = 0, HLBM_MEM_DEVICE = 1 } hlbm_mem;
+
+typedef enum { HLBM_NOISE_NONE = 0, HLBM_NOISE_RIM = 1, HLBM_NOISE_BOX = 2 } hlbm_noise;
+
+/* Fields for hlbm_get_field (n values each, or 3n for vectors, component-
+ * major).  RHO/U: current state.  MEAN_RHO/MEAN_U: window means.
+ * POROSITY: d.  MEAN_TAU: window mean of tau_eff. */
+typedef enum {
+  HLBM_FIELD_RHO = 0,
+  HLBM_FIELD_U = 1,
+  HLBM_FIELD_MEAN_RHO = 2,
+  HLBM_FIELD_MEAN_U = 3,
+  HLBM_FIELD_POROSITY = 4,
+  HLBM_FIELD_MEAN_TAU = 5
+} hlbm_field;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(hlbm_desc) */
+  int32_t stencil;        /* hlbm_stencil */
+  int32_t precision;      /* hlbm_precision */
+  int32_t nx, ny, nz;     /* nz = 1 for D2Q9; nx >= 2 */
+  double tau;             /* molecular relaxation time tau0 > 1/2 (nu = (tau0 - 1/2)/3) */
+  double smagorinsky_cs;  /* Cs >= 0; 0 disables the closure */
+  int32_t bc_x, bc_y, bc_z;   /* hlbm_bc; y and z may not be INLET_OUTLET */
+  int32_t inlet_profile;  /* hlbm_inlet (used with bc_x = INLET_OUTLET) */
+  double u_in;            /* uniform inflow speed or parabola maximum */
+  double force[3];        /* constant body force 3 w_i xi_i.G added after collision (tests) */
+  int32_t track_mean_populations; /* 1: the window also accumulates full mean populations */
+  void* stream;           /* hipStream_t or NULL */
+} hlbm_desc;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(hlbm_adjoint_opts) */
+  int32_t source;         /* hlbm_source */
+  double tau_adj;         /* adjoint relaxation time (Sec. 5.4 regularisation); <= 0: tau0 */
+  int32_t turb;           /* hlbm_turb (ignored without the closure) */
+  int64_t max_iters;      /* iterations (rounded up to an even number) */
+  double tol;             /* stop when max|phi_k - phi_(k-M)| <= tol max|phi_k|; 0 = run max_iters */
+  int64_t check_every;    /* M (rounded up to even), default 100 */
+  int32_t restart;        /* 1: start from phi = 0 and re-freeze the Jacobian data */
+} hlbm_adjoint_opts;
+
+typedef struct {
+  int64_t iters;          /* iterations performed by this call */
+  double residual;        /* last relative residual (or -1 if never checked) */
+} hlbm_adjoint_report;
+
+/* ---- lifetime ------------------------------------------------------------ */
+
+/* Allocate a lattice: populations (SoA, planes padded to 256 B), porosity,
+ * outlet buffers.  Porosity starts at 1, populations at rest equilibrium.
+ * Errors: INVALID (sizes, tau <= 1/2, Cs < 0, bad enums), OOM, DEVICE. */
+hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out);
+/* Free every device buffer of the handle (synchronises its stream). */
+void hlbm_destroy(hlbm_lattice lat);
+/* Device bytes a lattice needs with the window and adjoint buffers. */
+hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int with_adjoint,
+                                 uint64_t* bytes);
+
+/* ---- geometry and initial state (rows a1, a2) --------------------------- */
+
+/* Copy a porosity field d[n]; every value must be finite and in [0, 1]
+ * (checked on the host for host input, on the device for device input). */
+hlbm_status hlbm_set_porosity(hlbm_lattice lat, const double* d, int64_t n, int32_t mem);
+/* Build d on the device for a cylinder of diameter D centred at (xc, yc),
+ * axis along z: solid fraction chi = 1 for r <= R-1, (1 + cos(pi(r-R+1)/2))/2
+ * for R-1 < r < R+1, 0 beyond; d = 1 - chi (Sec. 5.1: d = 0 in the cylinder).
+ * noise[n] (may be NULL) holds caller-drawn values: RIM adds them to d where
+ * 0 < chi < 1, BOX adds them to chi where |x-xc|, |y-yc| <= box_half; both
+ * clamp to [0, 1]. */
+hlbm_status hlbm_build_cylinder(hlbm_lattice lat, double xc, double yc, double D,
+                                const double* noise, int64_t n, int32_t mem,
+                                int32_t noise_mode, double box_half);
+/* f_i = f_i^eq(rho0, d u) with u[3n] (component-major) or, if u is NULL, the
+ * inlet profile continued into the domain (INLET_OUTLET) or rest.  Resets the
+ * step parity, the window and the adjoint. */
+hlbm_status hlbm_init_equilibrium(hlbm_lattice lat, double rho0, const double* u, int64_t n,
+                                  int32_t mem);
+hlbm_status hlbm_set_populations(hlbm_lattice lat, const double* f, int64_t n_values,
+                                 int32_t mem);
+hlbm_status hlbm_get_populations(hlbm_lattice lat, double* f, int64_t n_values, int32_t mem);
+
+/* ---- objective (row a6) -------------------------------------------------- */
+
+/* Objective over the inclusive box lo..hi (a one-cell-thick plane for FFA).
+ * With INLET_OUTLET the box may not touch column 0.  u0, p0: FFA reference
+ * velocity and pressure (p0 = 1/3 for rho = 1). */
+hlbm_status hlbm_set_objective(hlbm_lattice lat, int32_t kind, const int32_t lo[3],
+                               const int32_t hi[3], double u0, double p0);
+
+/* ---- primal and window (rows a3, a4, a5) --------------------------------- */
+
+/* Advance n_steps collide-and-stream steps (in-place AA pattern).  If
+ * accumulate != 0 every step adds its pre-collision state to the FP64 window
+ * (rho, j, optional f, tau_eff, objective terms and dJ/df, dJ/dd
+ * coefficients).  If steady_tol > 0, every check_every steps the call stops
+ * once max|u(t) - u(t - check_every)| <= steady_tol max|u|.  *steps_done (may
+ * be NULL) receives the steps taken.  Returns DIVERGED on a non-finite check,
+ * W_NOT_CONVERGED if steady_tol > 0 was not met. */
+hlbm_status hlbm_run_primal(hlbm_lattice lat, int64_t n_steps, int32_t accumulate,
+                            double steady_tol, int64_t check_every, int64_t* steps_done);
+hlbm_status hlbm_window_reset(hlbm_lattice lat);
+hlbm_status hlbm_window_count(hlbm_lattice lat, int64_t* samples);
+/* which = 0: J of the current state; which = 1: window mean of J. */
+hlbm_status hlbm_get_objective(hlbm_lattice lat, int32_t which, double* J);
+
+/* ---- adjoint and gradient (rows a7, a8, a9) ------------------------------ */
+
+/* Freeze the Jacobian data (row a7) and iterate the adjoint sweep (row a8).
+ * Returns STATE without an objective (or without a window for MEAN, or
+ * without tracked mean populations for the differentiated closure). */
+hlbm_status hlbm_solve_adjoint(hlbm_lattice lat, const hlbm_adjoint_opts* opts,
+                               hlbm_adjoint_report* report);
+/* dJ/dd[n] (FP64), 0 on the inlet column (row a9). */
+hlbm_status hlbm_get_gradient(hlbm_lattice lat, double* g, int64_t n, int32_t mem);
+/* Adjoint populations phi on post-collision slots, canonical layout (q*n). */
+hlbm_status hlbm_get_adjoint(hlbm_lattice lat, double* phi, int64_t n_values, int32_t mem);
+
+/* ---- fields, timing, errors ---------------------------------------------- */
+
+hlbm_status hlbm_get_field(hlbm_lattice lat, int32_t field, double* out, int64_t n_values,
+                           int32_t mem);
+hlbm_status hlbm_synchronize(hlbm_lattice lat);
+/* Kernel-time bookkeeping by HIP events on the lattice's stream: with
+ * enable != 0 each primal and adjoint sweep batch is bracketed by events.
+ * hlbm_profile_get returns the summed milliseconds and kernel launch counts
+ * of the primal and adjoint sweeps since the last enable. */
+hlbm_status hlbm_profile_enable(hlbm_lattice lat, int32_t enable);
+hlbm_status hlbm_profile_get(hlbm_lattice lat, double* primal_ms, int64_t* primal_launches,
+                             double* adjoint_ms, int64_t* adjoint_launches);
+/* Algorithmic bytes per lattice update of the primal sweep (accumulate = 0 or
+ * 1) and of the adjoint sweep for this lattice's configuration. */
+hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* primal_window,
+                                  double* adjoint);
+const char* hlbm_status_string(hlbm_status s);
+const char* hlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

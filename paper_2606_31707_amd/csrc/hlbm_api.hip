@@ -1,0 +1,747 @@
+// hlbm_api.hip -- C ABI of the gfx950 HLBM mean-flow adjoint library: lattice
+// lifetime, argument checks, and the host-side loops of the three phases of
+// the paper's Algorithm 1 (primal with window, adjoint, gradient assembly).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hlbm_internal.hpp"
+
+using namespace hlbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hlbm_status fail(hlbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(HLBM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK_LAT(L)                                              \
+  do {                                                            \
+    if ((L) == nullptr) return fail(HLBM_E_INVALID, "null lattice"); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+hlbm_status dev_alloc(void** p, size_t bytes) {
+  if (*p) return HLBM_OK;
+  hipError_t e = hipMalloc(p, bytes ? bytes : 256);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(HLBM_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return HLBM_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int q_of(int stencil) { return stencil == HLBM_D2Q9 ? 9 : 19; }
+int dim_of(int stencil) { return stencil == HLBM_D2Q9 ? 2 : 3; }
+size_t ssize_of(int prec) { return prec == HLBM_FP64 ? 8 : (prec == HLBM_FP32 ? 4 : 2); }
+size_t dsize_of(int prec) { return prec == HLBM_FP64 ? 8 : 4; }
+size_t asize_of(int prec) { return prec == HLBM_FP64 ? 8 : 4; }
+int nsym_of(int stencil) { return stencil == HLBM_D2Q9 ? 3 : 6; }
+int ncoef_of(int stencil) { return 3 + dim_of(stencil) + nsym_of(stencil); }
+int nb_of(int stencil) { return 1 + dim_of(stencil) + nsym_of(stencil); }
+
+hlbm_status validate_desc(const hlbm_desc* d) {
+  if (!d) return fail(HLBM_E_INVALID, "null descriptor");
+  if (d->struct_size != sizeof(hlbm_desc))
+    return fail(HLBM_E_INVALID, "hlbm_desc.struct_size %u != %zu", d->struct_size, sizeof(hlbm_desc));
+  if (d->stencil != HLBM_D2Q9 && d->stencil != HLBM_D3Q19) return fail(HLBM_E_INVALID, "bad stencil");
+  if (d->precision < HLBM_FP64 || d->precision > HLBM_FP16S) return fail(HLBM_E_INVALID, "bad precision");
+  if (d->nx < 2 || d->ny < 1 || d->nz < 1) return fail(HLBM_E_INVALID, "bad lattice size");
+  if (d->stencil == HLBM_D2Q9 && d->nz != 1) return fail(HLBM_E_INVALID, "D2Q9 needs nz = 1");
+  if ((int64_t)d->nx * d->ny * d->nz > (int64_t)1 << 31) return fail(HLBM_E_INVALID, "lattice too large");
+  if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(HLBM_E_INVALID, "tau must exceed 1/2");
+  if (!(d->smagorinsky_cs >= 0.0) || !std::isfinite(d->smagorinsky_cs))
+    return fail(HLBM_E_INVALID, "Smagorinsky constant must be >= 0");
+  if (d->bc_x < 0 || d->bc_x > 2 || d->bc_y < 0 || d->bc_y > 1 || d->bc_z < 0 || d->bc_z > 1)
+    return fail(HLBM_E_INVALID, "bad boundary kinds (only x may be INLET_OUTLET)");
+  if (d->bc_x == HLBM_BC_INLET_OUTLET) {
+    if (d->inlet_profile != HLBM_INLET_UNIFORM && d->inlet_profile != HLBM_INLET_PARABOLIC)
+      return fail(HLBM_E_INVALID, "bad inlet profile");
+    if (d->nx < 3) return fail(HLBM_E_INVALID, "inlet/outlet channel needs nx >= 3");
+  }
+  if (!std::isfinite(d->u_in)) return fail(HLBM_E_INVALID, "u_in not finite");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->force[a])) return fail(HLBM_E_INVALID, "force not finite");
+  return HLBM_OK;
+}
+
+// device scratch for host <-> device exchange of FP64 arrays
+hlbm_status staging(hlbm_lattice_s* L, const double* in, int64_t count, int mem, double** dev,
+                    bool* owned) {
+  *owned = false;
+  if (mem == HLBM_MEM_DEVICE) {
+    *dev = const_cast<double*>(in);
+    return HLBM_OK;
+  }
+  void* p = nullptr;
+  hlbm_status s = dev_alloc(&p, sizeof(double) * (size_t)count);
+  if (s != HLBM_OK) return s;
+  *dev = (double*)p;
+  *owned = true;
+  if (in) {
+    hipError_t e = hipMemcpyAsync(p, in, sizeof(double) * count, hipMemcpyHostToDevice, L->stream);
+    if (e != hipSuccess) {
+      dev_free(p);
+      return fail(HLBM_E_DEVICE, "H2D copy: %s", hipGetErrorString(e));
+    }
+  }
+  return HLBM_OK;
+}
+
+hlbm_status finish_out(hlbm_lattice_s* L, double* dev, double* out, int64_t count, int mem, bool owned) {
+  hipError_t e = hipSuccess;
+  if (mem == HLBM_MEM_HOST) e = hipMemcpyAsync(out, dev, sizeof(double) * count, hipMemcpyDeviceToHost, L->stream);
+  hipError_t e2 = hipStreamSynchronize(L->stream);
+  if (owned) dev_free(dev);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "D2H copy: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(HLBM_E_DEVICE, "stream sync: %s", hipGetErrorString(e2));
+  return HLBM_OK;
+}
+
+hlbm_status ensure_window(hlbm_lattice_s* L) {
+  const int64_t P = L->plane;
+  hlbm_status s;
+  bool fresh = L->acc_rho == nullptr;
+  if ((s = dev_alloc((void**)&L->acc_rho, sizeof(double) * P)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->acc_j, sizeof(double) * P * L->dim)) != HLBM_OK) return s;
+  if (L->desc.track_mean_populations && (s = dev_alloc((void**)&L->acc_f, sizeof(double) * P * L->q)) != HLBM_OK)
+    return s;
+  if (L->desc.smagorinsky_cs > 0.0 && (s = dev_alloc((void**)&L->acc_tau, sizeof(double) * P)) != HLBM_OK) return s;
+  if (fresh) {
+    HIP_TRY(hipMemsetAsync(L->acc_rho, 0, sizeof(double) * P, L->stream));
+    HIP_TRY(hipMemsetAsync(L->acc_j, 0, sizeof(double) * P * L->dim, L->stream));
+    if (L->acc_f) HIP_TRY(hipMemsetAsync(L->acc_f, 0, sizeof(double) * P * L->q, L->stream));
+    if (L->acc_tau) HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * P, L->stream));
+  }
+  return HLBM_OK;
+}
+
+hlbm_status ensure_partials(hlbm_lattice_s* L, int64_t nvals) {
+  if (L->red_cap >= nvals) return HLBM_OK;
+  dev_free(L->red);
+  L->red = nullptr;
+  L->red_cap = 0;
+  hlbm_status s = dev_alloc((void**)&L->red, sizeof(double) * (size_t)nvals);
+  if (s == HLBM_OK) L->red_cap = nvals;
+  return s;
+}
+
+int64_t n_blocks(hlbm_lattice_s* L) {
+  dim3 g = cell_grid(L);
+  return (int64_t)g.x * g.y * g.z;
+}
+
+// Reduces partials to up to two doubles on the host.
+hlbm_status reduce_to_host(hlbm_lattice_s* L, int nblocks, int pairs, double* out) {
+  double* res = L->red + 2 * n_blocks(L);  // result slots after the partials
+  if (pairs)
+    HIP_TRY(launch_finalize_max2(L, L->red, nblocks, res));
+  else
+    HIP_TRY(launch_finalize_sum(L, L->red, nblocks, res));
+  HIP_TRY(hipMemcpyAsync(L->red_host, res, sizeof(double) * 2, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  out[0] = L->red_host[0];
+  if (pairs) out[1] = L->red_host[1];
+  return HLBM_OK;
+}
+
+void reset_window_counts(hlbm_lattice_s* L) { L->nsamp = 0; }
+
+hlbm_status zero_window(hlbm_lattice_s* L) {
+  const int64_t P = L->plane;
+  if (L->acc_rho) HIP_TRY(hipMemsetAsync(L->acc_rho, 0, sizeof(double) * P, L->stream));
+  if (L->acc_j) HIP_TRY(hipMemsetAsync(L->acc_j, 0, sizeof(double) * P * L->dim, L->stream));
+  if (L->acc_f) HIP_TRY(hipMemsetAsync(L->acc_f, 0, sizeof(double) * P * L->q, L->stream));
+  if (L->acc_tau) HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * P, L->stream));
+  if (L->acc_obj) HIP_TRY(hipMemsetAsync(L->acc_obj, 0, sizeof(double) * L->rplane * L->ncoef, L->stream));
+  L->nsamp = 0;
+  return HLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hlbm_last_error(void) { return g_last_error.c_str(); }
+
+const char* hlbm_status_string(hlbm_status s) {
+  switch (s) {
+    case HLBM_OK: return "ok";
+    case HLBM_W_NOT_CONVERGED: return "not converged";
+    case HLBM_E_INVALID: return "invalid argument";
+    case HLBM_E_OOM: return "out of device memory";
+    case HLBM_E_STATE: return "call order violated";
+    case HLBM_E_DIVERGED: return "diverged";
+    case HLBM_E_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int with_adjoint, uint64_t* bytes) {
+  hlbm_status s = validate_desc(desc);
+  if (s != HLBM_OK) return s;
+  if (!bytes) return fail(HLBM_E_INVALID, "null output");
+  const int q = q_of(desc->stencil), dim = dim_of(desc->stencil);
+  const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
+  const int64_t P = round_up(n, 128), G = round_up((int64_t)desc->ny * desc->nz, 128);
+  uint64_t b = (uint64_t)P * (q * ssize_of(desc->precision) + dsize_of(desc->precision)) +
+               (uint64_t)G * q * ssize_of(desc->precision);
+  if (with_window) {
+    b += (uint64_t)P * 8 * (1 + dim);
+    if (desc->track_mean_populations) b += (uint64_t)P * 8 * q;
+    if (desc->smagorinsky_cs > 0) b += (uint64_t)P * 8;
+  }
+  if (with_adjoint) {
+    const size_t as = asize_of(desc->precision);
+    b += (uint64_t)P * as * q;                                   // phi
+    b += (uint64_t)P * as * (dim + 2 + q + nb_of(desc->stencil)); // frozen coefficients
+    b += (uint64_t)P * 8 * (dim + 2);                            // gradient data
+    b += (uint64_t)G * (8 * (1 + dim) + 2 * as * q);
+  }
+  *bytes = b;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
+  if (!out) return fail(HLBM_E_INVALID, "null output handle");
+  *out = nullptr;
+  hlbm_status s = validate_desc(desc);
+  if (s != HLBM_OK) return s;
+  hlbm_lattice_s* L = new hlbm_lattice_s();
+  L->desc = *desc;
+  if (L->desc.stencil == HLBM_D2Q9) L->desc.bc_z = HLBM_BC_PERIODIC;
+  L->q = q_of(desc->stencil);
+  L->dim = dim_of(desc->stencil);
+  L->ncoef = ncoef_of(desc->stencil);
+  L->nb = nb_of(desc->stencil);
+  L->n = (int64_t)desc->nx * desc->ny * desc->nz;
+  L->plane = round_up(L->n, 128);
+  L->gplane = round_up((int64_t)desc->ny * desc->nz, 128);
+  L->ssize = ssize_of(desc->precision);
+  L->dsize = dsize_of(desc->precision);
+  L->asize = asize_of(desc->precision);
+  L->stream = (hipStream_t)desc->stream;
+  auto bail = [&](hlbm_status st) {
+    hlbm_destroy(L);
+    return st;
+  };
+  if ((s = dev_alloc(&L->f, L->ssize * L->q * L->plane)) != HLBM_OK) return bail(s);
+  if ((s = dev_alloc(&L->dpor, L->dsize * L->plane)) != HLBM_OK) return bail(s);
+  if ((s = dev_alloc(&L->ghost, L->ssize * L->q * L->gplane)) != HLBM_OK) return bail(s);
+  if ((s = ensure_partials(L, 2 * n_blocks(L) + 8)) != HLBM_OK) return bail(s);
+  if (hipHostMalloc((void**)&L->red_host, 4 * sizeof(double)) != hipSuccess)
+    return bail(fail(HLBM_E_OOM, "pinned host allocation failed"));
+  if (hipEventCreate(&L->ev0) != hipSuccess || hipEventCreate(&L->ev1) != hipSuccess)
+    return bail(fail(HLBM_E_DEVICE, "event creation failed"));
+  if (hipMemsetAsync(L->ghost, 0, L->ssize * L->q * L->gplane, L->stream) != hipSuccess)
+    return bail(fail(HLBM_E_DEVICE, "memset failed"));
+  // d = 1 everywhere: a cylinder of negative diameter leaves chi = 0
+  if (launch_cylinder(L, 0.0, 0.0, -10.0, nullptr, 0, 0.0) != hipSuccess)
+    return bail(fail(HLBM_E_DEVICE, "porosity fill failed"));
+  if (launch_init(L, 1.0, nullptr) != hipSuccess) return bail(fail(HLBM_E_DEVICE, "init failed"));
+  if (hipStreamSynchronize(L->stream) != hipSuccess) return bail(fail(HLBM_E_DEVICE, "sync failed"));
+  *out = L;
+  return HLBM_OK;
+}
+
+void hlbm_destroy(hlbm_lattice L) {
+  if (!L) return;
+  (void)hipStreamSynchronize(L->stream);
+  void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
+                  L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
+                  L->red, L->usnap};
+  for (void* p : bufs) dev_free(p);
+  if (L->red_host) (void)hipHostFree(L->red_host);
+  if (L->ev0) (void)hipEventDestroy(L->ev0);
+  if (L->ev1) (void)hipEventDestroy(L->ev1);
+  delete L;
+}
+
+hlbm_status hlbm_synchronize(hlbm_lattice L) {
+  CHECK_LAT(L);
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_set_porosity(hlbm_lattice L, const double* d, int64_t n, int32_t mem) {
+  CHECK_LAT(L);
+  if (!d || n != L->n) return fail(HLBM_E_INVALID, "porosity needs %lld values", (long long)L->n);
+  if (mem == HLBM_MEM_HOST) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!(d[i] >= 0.0 && d[i] <= 1.0)) return fail(HLBM_E_INVALID, "porosity[%lld] = %g outside [0, 1]", (long long)i, d[i]);
+  }
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, d, n, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  int* bad = nullptr;
+  if ((s = dev_alloc((void**)&bad, sizeof(int))) != HLBM_OK) {
+    if (owned) dev_free(dev);
+    return s;
+  }
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), L->stream);
+  if (e == hipSuccess) e = launch_set_porosity(L, dev, bad);
+  int hbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  dev_free(bad);
+  if (owned) dev_free(dev);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "set_porosity: %s", hipGetErrorString(e));
+  if (hbad) return fail(HLBM_E_INVALID, "porosity outside [0, 1] or not finite");
+  L->adj_ready = 0;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_build_cylinder(hlbm_lattice L, double xc, double yc, double D, const double* noise, int64_t n,
+                                int32_t mem, int32_t noise_mode, double box_half) {
+  CHECK_LAT(L);
+  if (!std::isfinite(xc) || !std::isfinite(yc) || !(D > 0.0) || !std::isfinite(D))
+    return fail(HLBM_E_INVALID, "bad cylinder parameters");
+  if (noise_mode < HLBM_NOISE_NONE || noise_mode > HLBM_NOISE_BOX) return fail(HLBM_E_INVALID, "bad noise mode");
+  if (noise && n != L->n) return fail(HLBM_E_INVALID, "noise needs %lld values", (long long)L->n);
+  double* dev = nullptr;
+  bool owned = false;
+  if (noise) {
+    hlbm_status s = staging(L, noise, n, mem, &dev, &owned);
+    if (s != HLBM_OK) return s;
+  }
+  hipError_t e = launch_cylinder(L, xc, yc, D, dev, noise ? noise_mode : 0, box_half);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (owned) dev_free(dev);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "build_cylinder: %s", hipGetErrorString(e));
+  L->adj_ready = 0;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_init_equilibrium(hlbm_lattice L, double rho0, const double* u, int64_t n, int32_t mem) {
+  CHECK_LAT(L);
+  if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(HLBM_E_INVALID, "rho0 must be positive");
+  if (u && n != 3 * L->n) return fail(HLBM_E_INVALID, "u needs 3n = %lld values", (long long)(3 * L->n));
+  double* dev = nullptr;
+  bool owned = false;
+  if (u) {
+    hlbm_status s = staging(L, u, 3 * L->n, mem, &dev, &owned);
+    if (s != HLBM_OK) return s;
+  }
+  hipError_t e = launch_init(L, rho0, dev);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (owned) dev_free(dev);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "init: %s", hipGetErrorString(e));
+  L->parity = 0;
+  L->steps = 0;
+  L->usnap_valid = 0;
+  L->adj_ready = 0;
+  return zero_window(L);
+}
+
+hlbm_status hlbm_set_populations(hlbm_lattice L, const double* f, int64_t n_values, int32_t mem) {
+  CHECK_LAT(L);
+  if (!f || n_values != L->q * L->n) return fail(HLBM_E_INVALID, "populations need q*n values");
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, f, n_values, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  hipError_t e = launch_scatter(L, dev);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (owned) dev_free(dev);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "set_populations: %s", hipGetErrorString(e));
+  L->parity = 0;
+  L->usnap_valid = 0;
+  L->adj_ready = 0;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_get_populations(hlbm_lattice L, double* f, int64_t n_values, int32_t mem) {
+  CHECK_LAT(L);
+  if (!f || n_values != L->q * L->n) return fail(HLBM_E_INVALID, "populations need q*n values");
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, mem == HLBM_MEM_DEVICE ? f : nullptr, n_values, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  hipError_t e = launch_gather(L, dev);
+  if (e != hipSuccess) {
+    if (owned) dev_free(dev);
+    return fail(HLBM_E_DEVICE, "gather: %s", hipGetErrorString(e));
+  }
+  return finish_out(L, dev, f, n_values, mem, owned);
+}
+
+hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3], const int32_t hi[3], double u0,
+                               double p0) {
+  CHECK_LAT(L);
+  if (kind < HLBM_OBJ_FFA || kind > HLBM_OBJ_MOMENTUM) return fail(HLBM_E_INVALID, "bad objective kind");
+  if (!lo || !hi) return fail(HLBM_E_INVALID, "null region");
+  const int nn[3] = {L->desc.nx, L->desc.ny, L->desc.nz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || hi[a] >= nn[a] || lo[a] > hi[a]) return fail(HLBM_E_INVALID, "region outside the lattice");
+  if (L->desc.bc_x == HLBM_BC_INLET_OUTLET && lo[0] < 1)
+    return fail(HLBM_E_INVALID, "region may not include the inlet column");
+  if (!std::isfinite(u0) || !std::isfinite(p0)) return fail(HLBM_E_INVALID, "u0/p0 not finite");
+  int rn[3];
+  for (int a = 0; a < 3; ++a) rn[a] = hi[a] - lo[a] + 1;
+  const int64_t rp = round_up((int64_t)rn[0] * rn[1] * rn[2], 128);
+  if (rp > L->rplane) {
+    dev_free(L->acc_obj);
+    dev_free(L->src);
+    L->acc_obj = nullptr;
+    L->src = nullptr;
+  }
+  hlbm_status s;
+  if ((s = dev_alloc((void**)&L->acc_obj, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->src, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
+  L->rplane = rp > L->rplane ? rp : L->rplane;
+  L->obj_kind = kind;
+  for (int a = 0; a < 3; ++a) {
+    L->lo[a] = lo[a];
+    L->rn[a] = rn[a];
+  }
+  L->u0 = u0;
+  L->p0 = p0;
+  L->obj_set = 1;
+  L->adj_ready = 0;
+  // a new objective starts a new window
+  return zero_window(L);
+}
+
+hlbm_status hlbm_window_reset(hlbm_lattice L) {
+  CHECK_LAT(L);
+  L->adj_ready = 0;
+  return zero_window(L);
+}
+
+hlbm_status hlbm_window_count(hlbm_lattice L, int64_t* samples) {
+  CHECK_LAT(L);
+  if (!samples) return fail(HLBM_E_INVALID, "null output");
+  *samples = L->nsamp;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_profile_enable(hlbm_lattice L, int32_t enable) {
+  CHECK_LAT(L);
+  L->prof = enable ? 1 : 0;
+  L->prim_ms = L->adj_ms = 0.0;
+  L->prim_launch = L->adj_launch = 0;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_profile_get(hlbm_lattice L, double* primal_ms, int64_t* primal_launches, double* adjoint_ms,
+                             int64_t* adjoint_launches) {
+  CHECK_LAT(L);
+  if (primal_ms) *primal_ms = L->prim_ms;
+  if (primal_launches) *primal_launches = L->prim_launch;
+  if (adjoint_ms) *adjoint_ms = L->adj_ms;
+  if (adjoint_launches) *adjoint_launches = L->adj_launch;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate, double steady_tol,
+                            int64_t check_every, int64_t* steps_done) {
+  CHECK_LAT(L);
+  if (steps_done) *steps_done = 0;
+  if (n_steps < 0) return fail(HLBM_E_INVALID, "negative step count");
+  if (!(steady_tol >= 0.0)) return fail(HLBM_E_INVALID, "steady_tol must be >= 0");
+  if (check_every <= 0) check_every = 100;
+  hlbm_status s;
+  if (accumulate) {
+    if ((s = ensure_window(L)) != HLBM_OK) return s;
+  }
+  if (steady_tol > 0.0) {
+    if ((s = dev_alloc((void**)&L->usnap, sizeof(double) * L->plane * L->dim)) != HLBM_OK) return s;
+  }
+  const int64_t nb = n_blocks(L);
+  // snapshot of u at the start of a steady run
+  if (steady_tol > 0.0) {
+    int nbl = 0;
+    HIP_TRY(launch_steady_check(L, 1, L->red, &nbl));
+    L->usnap_valid = 1;
+  }
+  (void)nb;
+  int64_t done = 0;
+  hlbm_status result = HLBM_OK;
+  bool converged = false;
+  // chunks between checks are timed as one batch
+  while (done < n_steps) {
+    int64_t chunk = n_steps - done;
+    if (steady_tol > 0.0 && chunk > check_every) chunk = check_every;
+    if (L->prof) HIP_TRY(hipEventRecord(L->ev0, L->stream));
+    for (int64_t k = 0; k < chunk; ++k) {
+      hipError_t e = launch_primal_step(L, accumulate);
+      if (e != hipSuccess) return fail(HLBM_E_DEVICE, "primal step: %s", hipGetErrorString(e));
+      L->parity ^= 1;
+      L->steps += 1;
+      if (accumulate) L->nsamp += 1;
+    }
+    if (L->prof) {
+      HIP_TRY(hipEventRecord(L->ev1, L->stream));
+      HIP_TRY(hipEventSynchronize(L->ev1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
+      L->prim_ms += ms;
+      L->prim_launch += chunk;
+    }
+    done += chunk;
+    if (steady_tol > 0.0) {
+      int nbl = 0;
+      HIP_TRY(launch_steady_check(L, 0, L->red, &nbl));
+      double mm[2];
+      if ((s = reduce_to_host(L, nbl, 1, mm)) != HLBM_OK) return s;
+      if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) {
+        if (steps_done) *steps_done = done;
+        return fail(HLBM_E_DIVERGED, "non-finite velocity after %lld steps", (long long)L->steps);
+      }
+      if (mm[0] <= steady_tol * mm[1]) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  if (steps_done) *steps_done = done;
+  if (L->prof == 0) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HLBM_E_DEVICE, "primal: %s", hipGetErrorString(e));
+  }
+  if (steady_tol > 0.0 && !converged) result = HLBM_W_NOT_CONVERGED;
+  L->adj_ready = 0;
+  return result;
+}
+
+hlbm_status hlbm_get_objective(hlbm_lattice L, int32_t which, double* J) {
+  CHECK_LAT(L);
+  if (!J) return fail(HLBM_E_INVALID, "null output");
+  if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
+  if (which == 1 && L->nsamp == 0) return fail(HLBM_E_STATE, "empty window");
+  if (which != 0 && which != 1) return fail(HLBM_E_INVALID, "which must be 0 or 1");
+  int nbl = 0;
+  HIP_TRY(launch_objective(L, which, L->red, &nbl));
+  return reduce_to_host(L, nbl, 0, J);
+}
+
+hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_adjoint_report* rep) {
+  CHECK_LAT(L);
+  if (!o || o->struct_size != sizeof(hlbm_adjoint_opts)) return fail(HLBM_E_INVALID, "bad adjoint options");
+  if (rep) {
+    rep->iters = 0;
+    rep->residual = -1.0;
+  }
+  if (o->source != HLBM_SOURCE_STEADY && o->source != HLBM_SOURCE_MEAN) return fail(HLBM_E_INVALID, "bad source");
+  if (o->turb != HLBM_TURB_FROZEN && o->turb != HLBM_TURB_DIFFERENTIATED) return fail(HLBM_E_INVALID, "bad turb");
+  if (o->max_iters < 0 || !(o->tol >= 0.0)) return fail(HLBM_E_INVALID, "bad iteration limits");
+  const double tau_adj = o->tau_adj > 0.0 ? o->tau_adj : L->desc.tau;
+  if (!(tau_adj > 0.5)) return fail(HLBM_E_INVALID, "tau_adj must exceed 1/2");
+  if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
+  const bool smag = L->desc.smagorinsky_cs > 0.0;
+  if (o->source == HLBM_SOURCE_MEAN) {
+    if (L->nsamp == 0 || !L->acc_rho) return fail(HLBM_E_STATE, "mean-flow adjoint needs a non-empty window");
+    if (smag && o->turb == HLBM_TURB_DIFFERENTIATED && !L->acc_f)
+      return fail(HLBM_E_STATE, "differentiated closure needs track_mean_populations");
+  }
+  const int P = 0;
+  (void)P;
+  const int64_t plane = L->plane;
+  const size_t as = L->asize;
+  hlbm_status s;
+  const int nprep = L->dim + 2 + L->q + L->nb;
+  if ((s = dev_alloc(&L->phi, as * L->q * plane)) != HLBM_OK) return s;
+  if ((s = dev_alloc(&L->prep, as * nprep * plane)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->gdat, sizeof(double) * (L->dim + 2) * plane)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->oprep, sizeof(double) * (1 + L->dim) * L->gplane)) != HLBM_OK) return s;
+  if ((s = dev_alloc(&L->pv[0], as * L->q * L->gplane)) != HLBM_OK) return s;
+  if ((s = dev_alloc(&L->pv[1], as * L->q * L->gplane)) != HLBM_OK) return s;
+  if (o->tol > 0.0 && (s = dev_alloc(&L->snap, as * L->q * plane)) != HLBM_OK) return s;
+  L->nprep = nprep;
+  const bool turb_diff = smag && o->turb == HLBM_TURB_DIFFERENTIATED;
+  if (o->restart || !L->adj_ready || L->adj_diff != (int)turb_diff) {
+    HIP_TRY(hipMemsetAsync(L->prep, 0, as * nprep * plane, L->stream));
+    HIP_TRY(hipMemsetAsync(L->gdat, 0, sizeof(double) * (L->dim + 2) * plane, L->stream));
+    HIP_TRY(hipMemsetAsync(L->src, 0, sizeof(double) * L->rplane * L->ncoef, L->stream));
+    HIP_TRY(launch_adjoint_prep(L, o->source, tau_adj, o->turb));
+    HIP_TRY(hipMemsetAsync(L->phi, 0, as * L->q * plane, L->stream));
+    HIP_TRY(hipMemsetAsync(L->pv[0], 0, as * L->q * L->gplane, L->stream));
+    HIP_TRY(hipMemsetAsync(L->pv[1], 0, as * L->q * L->gplane, L->stream));
+    L->pvcur = 0;
+    L->adj_iters = 0;
+    L->adj_ready = 1;
+    L->adj_les = smag ? 1 : 0;
+    L->adj_diff = turb_diff ? 1 : 0;
+    L->adj_omega = 1.0 / tau_adj;
+  }
+  int64_t iters = o->max_iters + (o->max_iters & 1);
+  int64_t M = o->check_every > 0 ? o->check_every : 100;
+  M += (M & 1);
+  hlbm_status result = HLBM_OK;
+  double res = -1.0;
+  if (o->tol > 0.0) {
+    int nbl = 0;
+    HIP_TRY(launch_adjoint_residual(L, 1, L->red, &nbl));
+  }
+  int64_t done = 0;
+  bool converged = false;
+  while (done < iters) {
+    int64_t chunk = iters - done;
+    if (o->tol > 0.0 && chunk > M) chunk = M;
+    if (L->prof) HIP_TRY(hipEventRecord(L->ev0, L->stream));
+    for (int64_t k = 0; k < chunk; ++k) {
+      hipError_t e = launch_adjoint_step(L);
+      if (e != hipSuccess) return fail(HLBM_E_DEVICE, "adjoint step: %s", hipGetErrorString(e));
+      L->pvcur ^= 1;
+      L->adj_iters += 1;
+    }
+    if (L->prof) {
+      HIP_TRY(hipEventRecord(L->ev1, L->stream));
+      HIP_TRY(hipEventSynchronize(L->ev1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
+      L->adj_ms += ms;
+      L->adj_launch += chunk;
+    }
+    done += chunk;
+    if (o->tol > 0.0) {
+      int nbl = 0;
+      HIP_TRY(launch_adjoint_residual(L, 0, L->red, &nbl));
+      double mm[2];
+      if ((s = reduce_to_host(L, nbl, 1, mm)) != HLBM_OK) return s;
+      if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) {
+        if (rep) rep->iters = done;
+        return fail(HLBM_E_DIVERGED, "non-finite adjoint after %lld iterations", (long long)L->adj_iters);
+      }
+      res = mm[1] > 0.0 ? mm[0] / mm[1] : mm[0];
+      if (res <= o->tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  if (rep) {
+    rep->iters = done;
+    rep->residual = res;
+  }
+  if (o->tol > 0.0 && !converged) result = HLBM_W_NOT_CONVERGED;
+  return result;
+}
+
+hlbm_status hlbm_get_gradient(hlbm_lattice L, double* g, int64_t n, int32_t mem) {
+  CHECK_LAT(L);
+  if (!g || n != L->n) return fail(HLBM_E_INVALID, "gradient needs n values");
+  if (!L->adj_ready) return fail(HLBM_E_STATE, "solve the adjoint first");
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, mem == HLBM_MEM_DEVICE ? g : nullptr, n, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  hipError_t e = launch_gradient(L, dev);
+  if (e != hipSuccess) {
+    if (owned) dev_free(dev);
+    return fail(HLBM_E_DEVICE, "gradient: %s", hipGetErrorString(e));
+  }
+  return finish_out(L, dev, g, n, mem, owned);
+}
+
+hlbm_status hlbm_get_adjoint(hlbm_lattice L, double* phi, int64_t n_values, int32_t mem) {
+  CHECK_LAT(L);
+  if (!phi || n_values != L->q * L->n) return fail(HLBM_E_INVALID, "adjoint needs q*n values");
+  if (!L->adj_ready) return fail(HLBM_E_STATE, "solve the adjoint first");
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, mem == HLBM_MEM_DEVICE ? phi : nullptr, n_values, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  hipError_t e = launch_adjoint_gather(L, dev);
+  if (e != hipSuccess) {
+    if (owned) dev_free(dev);
+    return fail(HLBM_E_DEVICE, "adjoint gather: %s", hipGetErrorString(e));
+  }
+  return finish_out(L, dev, phi, n_values, mem, owned);
+}
+
+}  // extern "C"
+
+namespace {
+template <typename Dd>
+__global__ void k_porosity_out(const Dd* __restrict__ d, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)d[i];
+}
+}  // namespace
+
+extern "C" hlbm_status hlbm_get_field(hlbm_lattice L, int32_t field, double* out, int64_t n_values, int32_t mem) {
+  CHECK_LAT(L);
+  if (!out) return fail(HLBM_E_INVALID, "null output");
+  const bool vec = (field == HLBM_FIELD_U || field == HLBM_FIELD_MEAN_U);
+  if (field < HLBM_FIELD_RHO || field > HLBM_FIELD_MEAN_TAU) return fail(HLBM_E_INVALID, "bad field");
+  const int64_t need = vec ? 3 * L->n : L->n;
+  if (n_values != need) return fail(HLBM_E_INVALID, "field needs %lld values", (long long)need);
+  if ((field == HLBM_FIELD_MEAN_RHO || field == HLBM_FIELD_MEAN_U || field == HLBM_FIELD_MEAN_TAU) &&
+      (L->nsamp == 0 || !L->acc_rho))
+    return fail(HLBM_E_STATE, "empty window");
+  if (field == HLBM_FIELD_MEAN_TAU && !L->acc_tau) return fail(HLBM_E_STATE, "no Smagorinsky closure");
+  double* dev;
+  bool owned;
+  hlbm_status s = staging(L, mem == HLBM_MEM_DEVICE ? out : nullptr, need, mem, &dev, &owned);
+  if (s != HLBM_OK) return s;
+  hipError_t e = hipSuccess;
+  if (field == HLBM_FIELD_RHO)
+    e = launch_moments(L, dev, nullptr);
+  else if (field == HLBM_FIELD_U)
+    e = launch_moments(L, nullptr, dev);
+  else if (field == HLBM_FIELD_POROSITY) {
+    const int64_t nb = (L->n + 255) / 256;
+    if (L->desc.precision == HLBM_FP64)
+      k_porosity_out<double><<<dim3((unsigned)nb), dim3(256), 0, L->stream>>>((const double*)L->dpor, dev, L->n);
+    else
+      k_porosity_out<float><<<dim3((unsigned)nb), dim3(256), 0, L->stream>>>((const float*)L->dpor, dev, L->n);
+    e = hipGetLastError();
+  } else {
+    e = launch_mean_fields(L, field, dev);
+  }
+  if (e != hipSuccess) {
+    if (owned) dev_free(dev);
+    return fail(HLBM_E_DEVICE, "get_field: %s", hipGetErrorString(e));
+  }
+  return finish_out(L, dev, out, need, mem, owned);
+}
+
+extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, double* primal_window, double* adjoint) {
+  CHECK_LAT(L);
+  const double q = L->q, dim = L->dim;
+  const double ss = (double)L->ssize, ds = (double)L->dsize, as = (double)L->asize;
+  const double rfrac = L->obj_set ? (double)L->rn[0] * L->rn[1] * L->rn[2] / (double)L->n : 0.0;
+  const bool smag = L->desc.smagorinsky_cs > 0.0;
+  // primal: read + write every population once, read d
+  const double p = 2.0 * q * ss + ds;
+  // window: FP64 read-modify-write of rho, j (+ f, tau) and the region terms
+  double pw = p + 16.0 * (1.0 + dim);
+  if (L->desc.track_mean_populations) pw += 16.0 * q;
+  if (smag) pw += 16.0;
+  pw += rfrac * 16.0 * L->ncoef;
+  // adjoint: read + write phi, read the frozen coefficients and the source
+  double a = 2.0 * q * as + as * (dim + 1.0);
+  if (smag) a += as;
+  if (L->adj_diff) a += as * (q + L->nb);
+  a += rfrac * 8.0 * (L->ncoef - 2);
+  if (primal) *primal = p;
+  if (primal_window) *primal_window = pw;
+  if (adjoint) *adjoint = a;
+  return HLBM_OK;
+}

@@ -1,0 +1,173 @@
+// hlbm_device.hpp -- device-side building blocks of the gfx950 HLBM sweeps.
+//
+// Populations are stored SoA (one plane per direction, planes padded to
+// 256 B), shifted by the lattice weights: the stored value of direction i is
+// s_i = f_i - w_i.  With sum w = 1 and sum w xi = 0 the moments become
+// rho = 1 + sum s, j = sum xi s, which keeps FP32/FP16 storage accurate for
+// the near-equilibrium states of these flows (f_i ~ w_i).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlbm {
+
+enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_INOUT = 2 };
+enum { OBJ_FFA = 0, OBJ_DISS = 1, OBJ_MOMENTUM = 2 };
+enum { NB_CELL = 0, NB_BOUNCE = 1, NB_OUTLET = 2, NB_DROP = 3 };
+
+constexpr int BX = 64;  // one wavefront along x: 64 consecutive cells per load
+constexpr int BY = 4;   // four rows per 256-thread workgroup
+
+// ---- velocity sets (Sec. 2.1: D2Q9 and D3Q19) ------------------------------
+template <int Q>
+struct Lat;
+
+template <>
+struct Lat<9> {
+  static constexpr int D = 2;
+  static constexpr int NSYM = 3;  // xx, yy, xy
+  static constexpr int cx[9] = {0, 1, 0, 1, -1, -1, 0, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int opp[9] = {0, 5, 6, 7, 8, 1, 2, 3, 4};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36,
+                                  1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36};
+};
+
+template <>
+struct Lat<19> {
+  static constexpr int D = 3;
+  static constexpr int NSYM = 6;  // xx, yy, zz, xy, xz, yz
+  static constexpr int cx[19] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+  static constexpr int cy[19] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+  static constexpr int opp[19] = {0, 10, 11, 12, 13, 14, 15, 16, 17, 18,
+                                  1, 2, 3, 4, 5, 6, 7, 8, 9};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+// Number of per-region-cell objective coefficients: J, dJ/dd, then the
+// quadratic form dJ/df_i = a0 + a1.xi_i + a2:xi_i xi_i (a2 symmetric).
+template <int Q>
+struct Coef {
+  static constexpr int J = 0, DJDD = 1, A0 = 2, A1 = 3;
+  static constexpr int A2 = A1 + Lat<Q>::D;
+  static constexpr int N = A2 + Lat<Q>::NSYM;
+  static constexpr int NB = 1 + Lat<Q>::D + Lat<Q>::NSYM;  // b0, b1, b2 of dtau/df
+};
+
+// ---- storage / compute types ----------------------------------------------
+template <typename S>
+struct Prec;
+template <>
+struct Prec<double> {
+  using T = double;   // arithmetic
+  using Dd = double;  // porosity storage
+};
+template <>
+struct Prec<float> {
+  using T = float;
+  using Dd = float;
+};
+template <>
+struct Prec<_Float16> {
+  using T = float;
+  using Dd = float;
+};
+
+// ---- geometry and boundary classification ---------------------------------
+struct Geo {
+  int nx, ny, nz;
+  int bcx, bcy, bcz;
+  int64_t plane;   // population plane stride (elements)
+  int64_t gplane;  // outlet (y, z) plane stride (elements)
+  int inlet_profile;
+  double u_in;
+};
+
+__device__ __forceinline__ int64_t cell_of(const Geo& g, int x, int y, int z) {
+  return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+}
+
+// Classifies the lattice position (x, y, z) reached from a cell: wraps the
+// periodic axes in place; a wall crossing (halfway bounce-back) takes
+// precedence over the inlet/outlet ends of the x axis.
+__device__ __forceinline__ int classify(const Geo& g, int& x, int& y, int& z) {
+  int bounce = 0;
+  if (y < 0 || y >= g.ny) {
+    if (g.bcy == BC_PERIODIC)
+      y = (y < 0) ? y + g.ny : y - g.ny;
+    else
+      bounce = 1;
+  }
+  if (z < 0 || z >= g.nz) {
+    if (g.bcz == BC_PERIODIC)
+      z = (z < 0) ? z + g.nz : z - g.nz;
+    else
+      bounce = 1;
+  }
+  if (x < 0 || x >= g.nx) {
+    if (g.bcx == BC_PERIODIC)
+      x = (x < 0) ? x + g.nx : x - g.nx;
+    else if (g.bcx == BC_WALLS)
+      bounce = 1;
+    else if (!bounce)
+      return (x >= g.nx) ? NB_OUTLET : NB_DROP;
+  }
+  return bounce ? NB_BOUNCE : NB_CELL;
+}
+
+// Inlet velocity u_in(y): uniform, or the parabola vanishing at the halfway
+// walls y = -1/2 and y = ny - 1/2.
+template <typename T>
+__device__ __forceinline__ T inlet_velocity(const Geo& g, int y) {
+  if (g.inlet_profile == 2) {
+    const double H = (double)g.ny;
+    return (T)(4.0 * g.u_in * (y + 0.5) * (H - 0.5 - y) / (H * H));
+  }
+  return (T)g.u_in;
+}
+
+// ---- block reductions (deterministic: fixed lane / wave order) -------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over a 256-thread block; result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* lds) {
+  const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  v = wave_sum(v);
+  if ((t & 63) == 0) lds[t >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (t == 0) r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max256(double v, double* lds) {
+  const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  v = wave_max(v);
+  if ((t & 63) == 0) lds[t >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (t == 0) r = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int linear_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+}  // namespace hlbm

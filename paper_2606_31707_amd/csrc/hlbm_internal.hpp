@@ -1,0 +1,123 @@
+// hlbm_internal.hpp -- host-side lattice state shared by the C ABI and the
+// kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hlbm.h"
+#include "hlbm_device.hpp"
+
+struct hlbm_lattice_s {
+  hlbm_desc desc;
+  int q = 0, dim = 0, ncoef = 0, nb = 0;
+  int64_t n = 0;       // cells
+  int64_t plane = 0;   // padded plane stride (elements)
+  int64_t gplane = 0;  // padded (y, z) plane stride of the outlet buffers
+  size_t ssize = 0;    // bytes per stored population
+  size_t dsize = 0;    // bytes per porosity value
+  hipStream_t stream = nullptr;
+
+  // primal state
+  void* f = nullptr;      // q * plane stored populations (AA pattern, in place)
+  void* dpor = nullptr;   // plane porosity values
+  void* ghost = nullptr;  // q * gplane outlet virtual values (even -> odd step)
+  int parity = 0;         // 0: canonical layout; 1: after an even (local) step
+  int64_t steps = 0;
+
+  // window (FP64)
+  double* acc_rho = nullptr;  // plane: sum of (rho - 1)
+  double* acc_j = nullptr;    // dim * plane
+  double* acc_f = nullptr;    // q * plane: sum of f_i - w_i (optional)
+  double* acc_tau = nullptr;  // plane: sum of tau_eff (with the closure)
+  double* acc_obj = nullptr;  // ncoef * rplane
+  int64_t nsamp = 0;
+
+  // objective region
+  int obj_set = 0, obj_kind = 0;
+  int lo[3] = {0, 0, 0}, rn[3] = {1, 1, 1};
+  int64_t rplane = 0;
+  double u0 = 0.0, p0 = 1.0 / 3.0;
+
+  // adjoint
+  void* phi = nullptr;    // q * plane (double for FP64, float otherwise)
+  void* prep = nullptr;   // per-cell frozen coefficients (adjoint type)
+  int nprep = 0;          // planes in prep
+  double* src = nullptr;  // ncoef * rplane: adjoint source and dJ/dd on the region
+  double* gdat = nullptr; // (dim + 2) * plane: rho, u, omega for the gradient
+  double* oprep = nullptr;// (1 + dim) * gplane: rho, u of the outlet column
+  void* pv[2] = {nullptr, nullptr};  // q * gplane: adjoint on the outlet virtual slots
+  int pvcur = 0;
+  void* snap = nullptr;   // q * plane residual snapshot
+  size_t asize = 0;       // bytes per adjoint value
+  int adj_ready = 0;
+  int adj_diff = 0;       // differentiated closure term active
+  int adj_les = 0;        // per-cell omega
+  double adj_omega = 0.0; // 1/tau_adj when uniform
+  int64_t adj_iters = 0;
+
+  // reductions
+  double* red = nullptr;      // partials
+  int64_t red_cap = 0;
+  double* red_host = nullptr; // pinned
+  double* usnap = nullptr;    // dim * plane steady-check snapshot
+  int usnap_valid = 0;
+
+  // profiling
+  int prof = 0;
+  double prim_ms = 0.0, adj_ms = 0.0;
+  int64_t prim_launch = 0, adj_launch = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace hlbm {
+
+// Per-launch collision parameters.
+struct Coll {
+  double tau0, omega0;
+  double kS;      // 18 sqrt(2) Cs^2
+  int smag;       // closure on
+  double force[3];
+};
+
+struct ObjBox {
+  int active, kind;
+  int lo[3], rn[3];
+  int64_t rplane;
+  double u0, p0, tau0;
+};
+
+struct Acc {
+  double* rho;
+  double* j;
+  double* f;
+  double* tau;
+  double* obj;
+};
+
+Geo make_geo(const hlbm_lattice_s* L);
+ObjBox make_obj(const hlbm_lattice_s* L);
+Coll make_coll(const hlbm_lattice_s* L);
+dim3 cell_grid(const hlbm_lattice_s* L);
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev);
+hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
+                           const double* noise_dev, int mode, double box_half);
+hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev);
+hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate);
+hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev);
+hipError_t launch_scatter(hlbm_lattice_s* L, const double* in_dev);
+hipError_t launch_moments(hlbm_lattice_s* L, double* rho_dev, double* u_dev);
+hipError_t launch_mean_fields(hlbm_lattice_s* L, int field, double* out_dev);
+hipError_t launch_steady_check(hlbm_lattice_s* L, int first, double* partials, int* nblocks);
+hipError_t launch_objective(hlbm_lattice_s* L, int which, double* partials, int* nblocks);
+hipError_t launch_finalize_sum(hlbm_lattice_s* L, const double* partials, int n, double* out);
+hipError_t launch_finalize_max2(hlbm_lattice_s* L, const double* partials, int n, double* out);
+hipError_t launch_adjoint_prep(hlbm_lattice_s* L, int source, double tau_adj, int turb);
+hipError_t launch_adjoint_step(hlbm_lattice_s* L);
+hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partials, int* nblocks);
+hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev);
+hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev);
+
+}  // namespace hlbm

@@ -1,0 +1,1272 @@
+// hlbm_kernels.hip -- gfx950 kernels of the HLBM mean-flow adjoint path.
+//
+// Propagation is the in-place AA pattern: the even step reads a cell's own
+// slots and writes its post-collision values back swapped (slot opp(i)); the
+// odd step pulls the neighbours' swapped values, collides, and pushes to the
+// neighbours' slots.  Each cell reads and writes the same slot set in both
+// steps, so one population array suffices and every slot is read and written
+// exactly once per step.  All boundary conditions are resolved inside the
+// odd step's pull/push; the pressure outlet additionally uses a small ghost
+// buffer (even step -> odd step) for the values of its virtual column.
+//
+// The adjoint sweep (Eqs. adjoint_steady/adjoint_unsteady) runs on relabelled
+// adjoint populations phihat_k = phi_opp(k), which turns "collide at x, then
+// move against xi_i" into the same forward AA propagation; halfway bounce-back
+// is self-adjoint, the pinned inlet contributes zeros, and the outlet's
+// virtual column becomes a double-buffered array of adjoint values.
+//
+// All reductions are deterministic: wavefront shuffles, four waves through
+// LDS, per-block partials, one final single-block pass in a fixed order.
+#include <cmath>
+
+#include "hlbm_internal.hpp"
+
+namespace hlbm {
+
+// =========================================================================
+// small helpers
+// =========================================================================
+
+template <int Q, typename T>
+__device__ __forceinline__ void cell_moments(const T (&s)[Q], T& drho, T& jx, T& jy, T& jz) {
+  using L = Lat<Q>;
+  drho = 0;
+  jx = 0;
+  jy = 0;
+  jz = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    drho += s[k];
+    if (L::cx[k] > 0) jx += s[k];
+    if (L::cx[k] < 0) jx -= s[k];
+    if (L::cy[k] > 0) jy += s[k];
+    if (L::cy[k] < 0) jy -= s[k];
+    if (L::cz[k] > 0) jz += s[k];
+    if (L::cz[k] < 0) jz -= s[k];
+  }
+}
+
+// Non-equilibrium momentum flux with respect to f^eq(rho, u) from shifted
+// populations: Pi_ab = sum xi_a xi_b s - (drho/3) delta_ab - j_a j_b / rho.
+// Order: xx, yy, zz, xy, xz, yz (zz, xz, yz zero in 2D).
+template <int Q, typename T>
+__device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T jz, T ir,
+                                         T (&P)[6]) {
+  using L = Lat<Q>;
+  T pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (L::cx[k] != 0) pxx += s[k];
+    if (L::cy[k] != 0) pyy += s[k];
+    if (L::cz[k] != 0) pzz += s[k];
+    if (L::cx[k] * L::cy[k] > 0) pxy += s[k];
+    if (L::cx[k] * L::cy[k] < 0) pxy -= s[k];
+    if (L::cx[k] * L::cz[k] > 0) pxz += s[k];
+    if (L::cx[k] * L::cz[k] < 0) pxz -= s[k];
+    if (L::cy[k] * L::cz[k] > 0) pyz += s[k];
+    if (L::cy[k] * L::cz[k] < 0) pyz -= s[k];
+  }
+  const T d3 = drho / (T)3;
+  P[0] = pxx - d3 - jx * jx * ir;
+  P[1] = pyy - d3 - jy * jy * ir;
+  P[3] = pxy - jx * jy * ir;
+  if (Lat<Q>::D == 3) {
+    P[2] = pzz - d3 - jz * jz * ir;
+    P[4] = pxz - jx * jz * ir;
+    P[5] = pyz - jy * jz * ir;
+  } else {
+    P[2] = 0;
+    P[4] = 0;
+    P[5] = 0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T frob2(const T (&P)[6]) {
+  return P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + (T)2 * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
+}
+
+// Symmetric-tensor storage used by the quadratic forms: 2D (xx, yy, xy),
+// 3D (xx, yy, zz, xy, xz, yz).
+template <int Q>
+__device__ __forceinline__ int sym_index(int m6) {
+  // maps 6-vector index to the compact storage index (or -1 if absent in 2D)
+  if (Lat<Q>::D == 3) return m6;
+  return m6 == 0 ? 0 : (m6 == 1 ? 1 : (m6 == 3 ? 2 : -1));
+}
+
+// a0 + a1.xi_i + a2:xi_i xi_i for a compact coefficient vector a.
+template <int Q, typename T>
+__device__ __forceinline__ T quad_eval(const T* a, int i) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  const T x = (T)L::cx[i], y = (T)L::cy[i], z = (T)L::cz[i];
+  T r = a[0] + a[1] * x + a[2] * y;
+  if (D == 3) {
+    r += a[3] * z;
+    r += a[4] * x * x + a[5] * y * y + a[6] * z * z + (T)2 * (a[7] * x * y + a[8] * x * z + a[9] * y * z);
+  } else {
+    r += a[3] * x * x + a[4] * y * y + (T)2 * a[5] * x * y;
+  }
+  return r;
+}
+
+// Objective terms of one region cell (Sec. 4, Eqs. obj_ffa and obj_diss),
+// FP64: J, dJ/dd and the coefficients of dJ/df_i = a0 + a1.xi + a2:xi xi.
+template <int Q>
+__device__ void objective_terms(const ObjBox& ob, double d, double drho, double jx, double jy,
+                                double jz, const double (&P)[6], double* out) {
+  using C = Coef<Q>;
+  constexpr int D = Lat<Q>::D;
+#pragma unroll
+  for (int m = 0; m < C::N; ++m) out[m] = 0.0;
+  const double rho = 1.0 + drho, ir = 1.0 / rho;
+  const double u[3] = {jx * ir, jy * ir, jz * ir};
+  if (ob.kind == OBJ_FFA) {
+    // J = rho (u_x u0 - u_x^2) + p0 - rho/3 ; dJ/df_i = u0 xi_x - 2 u_x xi_x + u_x^2 - 1/3
+    out[C::J] = jx * ob.u0 - jx * jx * ir + ob.p0 - rho / 3.0;
+    out[C::A0] = u[0] * u[0] - 1.0 / 3.0;
+    out[C::A1] = ob.u0 - 2.0 * u[0];
+  } else if (ob.kind == OBJ_DISS) {
+    // J = cS Pi:Pi + cD |u|^2, cS = 9 nu/(2 tau0^2), cD = (1 - d)/tau0;
+    // dJ/df_i = 2 cS Pi:[(xi-u)(xi-u) - I/3] + 2 cD u.(xi - u)/rho
+    const double nu = (ob.tau0 - 0.5) / 3.0;
+    const double cS = 9.0 * nu / (2.0 * ob.tau0 * ob.tau0);
+    const double cD = (1.0 - d) / ob.tau0;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
+    double Pu[3], uPu = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      Pu[a] = Pm[a][0] * u[0] + Pm[a][1] * u[1] + Pm[a][2] * u[2];
+      uPu += u[a] * Pu[a];
+    }
+    const double tr = P[0] + P[1] + P[2];
+    out[C::J] = cS * frob2(P) + cD * uu;
+    out[C::DJDD] = -uu / ob.tau0;
+    out[C::A0] = 2.0 * cS * (uPu - tr / 3.0) - 2.0 * cD * uu * ir;
+    for (int a = 0; a < D; ++a) out[C::A1 + a] = -4.0 * cS * Pu[a] + 2.0 * cD * u[a] * ir;
+    for (int m6 = 0; m6 < 6; ++m6) {
+      const int m = sym_index<Q>(m6);
+      if (m >= 0) out[C::A2 + m] = 2.0 * cS * P[m6];
+    }
+  } else {
+    out[C::J] = jx;
+    out[C::A1] = 1.0;
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ bool region_index(const ObjBox& ob, int x, int y, int z, int64_t& r) {
+  const int rx = x - ob.lo[0], ry = y - ob.lo[1], rz = z - ob.lo[2];
+  if (!ob.active || rx < 0 || ry < 0 || rz < 0 || rx >= ob.rn[0] || ry >= ob.rn[1] || rz >= ob.rn[2])
+    return false;
+  r = (int64_t)rx + (int64_t)ob.rn[0] * ((int64_t)ry + (int64_t)ob.rn[1] * rz);
+  return true;
+}
+
+// AA odd-step pull of direction k into cell (x, y, z): post-collision value of
+// the upstream cell (stored swapped), bounce-back from the own cell, or the
+// outlet's virtual column.
+template <int Q, typename S, typename T>
+__device__ __forceinline__ T pull(const Geo& g, const S* __restrict__ A, const S* __restrict__ ghost,
+                                  int x, int y, int z, int64_t cell, int k) {
+  using L = Lat<Q>;
+  int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+  const int t = classify(g, sx, sy, sz);
+  if (t == NB_BOUNCE) return (T)A[k * g.plane + cell];
+  if (t == NB_OUTLET) return (T)ghost[k * g.gplane + sy + (int64_t)g.ny * sz];
+  return (T)A[L::opp[k] * g.plane + cell_of(g, sx, sy, sz)];
+}
+
+// AA odd-step push of direction k from cell (x, y, z).
+template <int Q, typename S>
+__device__ __forceinline__ void push(const Geo& g, S* __restrict__ A, int x, int y, int z,
+                                     int64_t cell, int k, S v) {
+  using L = Lat<Q>;
+  int tx = x + L::cx[k], ty = y + L::cy[k], tz = z + L::cz[k];
+  const int t = classify(g, tx, ty, tz);
+  if (t == NB_BOUNCE)
+    A[L::opp[k] * g.plane + cell] = v;
+  else if (t == NB_CELL)
+    A[k * g.plane + cell_of(g, tx, ty, tz)] = v;
+  // NB_OUTLET / NB_DROP: the population leaves the domain
+}
+
+// Canonical (post-stream) state of a cell for either step parity.
+template <int Q, typename S, typename T>
+__device__ __forceinline__ void load_state(const Geo& g, const S* __restrict__ A,
+                                           const S* __restrict__ ghost, int parity, int x, int y,
+                                           int z, int64_t cell, T (&s)[Q]) {
+  if (parity == 0) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s[k] = (T)A[k * g.plane + cell];
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s[k] = pull<Q, S, T>(g, A, ghost, x, y, z, cell, k);
+  }
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
+  using L = Lat<Q>;
+  const T ui = inlet_velocity<T>(g, y);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const T cu = (T)L::cx[k] * ui;
+    s[k] = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * ui * ui);
+  }
+}
+
+#define CELL_PROLOGUE                                   \
+  const int x = blockIdx.x * BX + threadIdx.x;          \
+  const int y = blockIdx.y * BY + threadIdx.y;          \
+  const int z = blockIdx.z;                             \
+  const bool valid = (x < g.nx) && (y < g.ny);          \
+  const int64_t cell = valid ? cell_of(g, x, y, z) : 0; \
+  const bool inout = (g.bcx == BC_INOUT);               \
+  (void)inout;
+
+// =========================================================================
+// primal sweep (rows a3, a4, a5): HLBM-BGK collision (Eq. hlbm) toward
+// f^eq(rho, d u), optional Smagorinsky tau_eff (Eqs. turbVisc, tauEff),
+// AA propagation with boundaries, fused FP64 window accumulation.
+// =========================================================================
+
+template <int Q, typename S, bool ODD, bool ACC>
+__global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const ObjBox ob,
+                                                S* __restrict__ A,
+                                                const typename Prec<S>::Dd* __restrict__ dpor,
+                                                S* __restrict__ ghost, const Acc acc) {
+  using L = Lat<Q>;
+  using T = typename Prec<S>::T;
+  CELL_PROLOGUE
+  if (!valid) return;
+  T s[Q];
+  if (inout && x == 0) {  // pinned equilibrium inlet: not collided, source only
+    inlet_state<Q, T>(g, y, s);
+    if (!ODD) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) A[L::opp[k] * g.plane + cell] = (S)s[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+    }
+    return;
+  }
+  load_state<Q, S, T>(g, A, ghost, ODD ? 1 : 0, x, y, z, cell, s);
+
+  T drho, jx, jy, jz;
+  cell_moments<Q, T>(s, drho, jx, jy, jz);
+  const T rho = (T)1 + drho;
+  const T ir = (T)1 / rho;
+  const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+
+  T omega = (T)c.omega0;
+  T taue = (T)c.tau0;
+  if (c.smag) {
+    T P[6];
+    neq_flux<Q, T>(s, drho, jx, jy, jz, ir, P);
+    const T tau0 = (T)c.tau0;
+    taue = (T)0.5 * (tau0 + sqrt(tau0 * tau0 + (T)c.kS * sqrt(frob2(P))));
+    omega = (T)1 / taue;
+  }
+
+  if (ACC) {
+    acc.rho[cell] += (double)drho;
+    acc.j[cell] += (double)jx;
+    acc.j[g.plane + cell] += (double)jy;
+    if (L::D == 3) acc.j[2 * g.plane + cell] += (double)jz;
+    if (acc.f) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc.f[k * g.plane + cell] += (double)s[k];
+    }
+    if (acc.tau) acc.tau[cell] += (double)taue;
+    int64_t r;
+    if (region_index<Q>(ob, x, y, z, r)) {
+      double sd[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
+      double dr, ax, ay, az, P[6];
+      cell_moments<Q, double>(sd, dr, ax, ay, az);
+      neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
+      double terms[Coef<Q>::N];
+      objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
+#pragma unroll
+      for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
+    }
+  }
+
+  const bool outlet = inout && (x == g.nx - 1);
+  const T uu = ux * ux + uy * uy + uz * uz;
+  const T d = (T)dpor[cell];
+  const T tx = d * ux, ty = d * uy, tz = d * uz;
+  const T tt = tx * tx + ty * ty + tz * tz;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const T cu = (T)L::cx[k] * tx + (T)L::cy[k] * ty + (T)L::cz[k] * tz;
+    const T feqs = (T)L::w[k] * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt));
+    const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)c.force[0] + (T)L::cy[k] * (T)c.force[1] +
+                                        (T)L::cz[k] * (T)c.force[2]);
+    s[k] = s[k] + omega * (feqs - s[k]) + fk;
+  }
+
+  if (!ODD) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) A[L::opp[k] * g.plane + cell] = (S)s[k];
+    if (outlet) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] != -1) continue;
+        const T cu = (T)L::cx[k] * ux + (T)L::cy[k] * uy + (T)L::cz[k] * uz;
+        const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
+        ghost[k * g.gplane + y + (int64_t)g.ny * z] = (S)vs;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+    if (outlet) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] != -1) continue;
+        int vx = x, vy = y + L::cy[k], vz = z + L::cz[k];
+        if (classify(g, vx, vy, vz) != NB_CELL) continue;
+        const T cu = (T)L::cx[k] * ux + (T)L::cy[k] * uy + (T)L::cz[k] * uz;
+        const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
+        A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
+      }
+    }
+  }
+}
+
+// =========================================================================
+// geometry, initial state, population exchange (rows a1, a2)
+// =========================================================================
+
+template <typename Dd>
+__global__ __launch_bounds__(256) void k_cylinder(const Geo g, Dd* __restrict__ dpor, double xc,
+                                                  double yc, double D, const double* __restrict__ noise,
+                                                  int mode, double box_half) {
+  CELL_PROLOGUE
+  if (!valid) return;
+  const double R = 0.5 * D;
+  const double dx = x - xc, dy = y - yc;
+  const double r = sqrt(dx * dx + dy * dy);
+  double chi;
+  if (r <= R - 1.0)
+    chi = 1.0;
+  else if (r >= R + 1.0)
+    chi = 0.0;
+  else
+    chi = 0.5 * (1.0 + cos(M_PI * (r - R + 1.0) * 0.5));
+  double d = 1.0 - chi;
+  if (noise != nullptr && mode == 1 && chi > 0.0 && chi < 1.0) {
+    d = fmin(1.0, fmax(0.0, d + noise[cell]));
+  } else if (noise != nullptr && mode == 2 && fabs(dx) <= box_half && fabs(dy) <= box_half) {
+    d = 1.0 - fmin(1.0, fmax(0.0, chi + noise[cell]));
+  }
+  dpor[cell] = (Dd)d;
+}
+
+template <typename Dd>
+__global__ __launch_bounds__(256) void k_set_porosity(const Geo g, Dd* __restrict__ dpor,
+                                                      const double* __restrict__ d, int* bad) {
+  CELL_PROLOGUE
+  if (!valid) return;
+  const double v = d[cell];
+  if (!(v >= 0.0 && v <= 1.0)) atomicOr(bad, 1);
+  dpor[cell] = (Dd)v;
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_init(const Geo g, S* __restrict__ A,
+                                              const typename Prec<S>::Dd* __restrict__ dpor,
+                                              double rho0, const double* __restrict__ u, int64_t n) {
+  using L = Lat<Q>;
+  CELL_PROLOGUE
+  if (!valid) return;
+  double s[Q];
+  if (inout && x == 0) {
+    inlet_state<Q, double>(g, y, s);
+  } else {
+    double v[3] = {0.0, 0.0, 0.0};
+    if (u != nullptr) {
+      v[0] = u[cell];
+      v[1] = u[n + cell];
+      v[2] = u[2 * n + cell];
+    } else if (inout) {
+      v[0] = inlet_velocity<double>(g, y);
+    }
+    const double d = (double)dpor[cell];
+    for (int a = 0; a < 3; ++a) v[a] *= d;
+    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const double cu = L::cx[k] * v[0] + L::cy[k] * v[1] + L::cz[k] * v[2];
+      s[k] = L::w[k] * ((rho0 - 1.0) + rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (S)s[k];
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_gather(const Geo g, const S* __restrict__ A,
+                                                const S* __restrict__ ghost, int parity,
+                                                double* __restrict__ out, int64_t n) {
+  using L = Lat<Q>;
+  using T = typename Prec<S>::T;
+  CELL_PROLOGUE
+  if (!valid) return;
+  T s[Q];
+  if (inout && x == 0)
+    inlet_state<Q, T>(g, y, s);
+  else
+    load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) out[k * n + cell] = (double)s[k] + L::w[k];
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_scatter(const Geo g, S* __restrict__ A,
+                                                 const double* __restrict__ in, int64_t n) {
+  using L = Lat<Q>;
+  CELL_PROLOGUE
+  if (!valid) return;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (S)(in[k * n + cell] - L::w[k]);
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_moments(const Geo g, const S* __restrict__ A,
+                                                 const S* __restrict__ ghost, int parity,
+                                                 double* __restrict__ rho, double* __restrict__ u,
+                                                 int64_t n) {
+  using T = typename Prec<S>::T;
+  CELL_PROLOGUE
+  if (!valid) return;
+  T s[Q];
+  if (inout && x == 0)
+    inlet_state<Q, T>(g, y, s);
+  else
+    load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+  double sd[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
+  double dr, jx, jy, jz;
+  cell_moments<Q, double>(sd, dr, jx, jy, jz);
+  const double r = 1.0 + dr;
+  if (rho) rho[cell] = r;
+  if (u) {
+    u[cell] = jx / r;
+    u[n + cell] = jy / r;
+    u[2 * n + cell] = jz / r;
+  }
+}
+
+// field: 2 mean rho, 3 mean u, 5 mean tau
+template <int Q>
+__global__ __launch_bounds__(256) void k_mean_fields(const Geo g, int field, const double* acc_rho,
+                                                     const double* acc_j, const double* acc_tau,
+                                                     double inv, double* __restrict__ out, int64_t n) {
+  CELL_PROLOGUE
+  if (!valid) return;
+  const double r = 1.0 + acc_rho[cell] * inv;
+  if (field == 2) {
+    out[cell] = r;
+  } else if (field == 3) {
+    out[cell] = acc_j[cell] * inv / r;
+    out[n + cell] = acc_j[g.plane + cell] * inv / r;
+    out[2 * n + cell] = (Lat<Q>::D == 3) ? acc_j[2 * g.plane + cell] * inv / r : 0.0;
+  } else {
+    out[cell] = acc_tau ? acc_tau[cell] * inv : 0.0;
+  }
+}
+
+// =========================================================================
+// reductions: steady check, objective
+// =========================================================================
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_steady_check(const Geo g, const S* __restrict__ A,
+                                                      const S* __restrict__ ghost, int parity,
+                                                      double* __restrict__ usnap, int first,
+                                                      double* __restrict__ partials) {
+  using T = typename Prec<S>::T;
+  __shared__ double lds[4];
+  CELL_PROLOGUE
+  double dmax = 0.0, umax = 0.0;
+  bool bad = false;
+  if (valid && !(inout && x == 0)) {
+    T s[Q];
+    load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+    double sd[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
+    double dr, jx, jy, jz;
+    cell_moments<Q, double>(sd, dr, jx, jy, jz);
+    const double r = 1.0 + dr;
+    const double u[3] = {jx / r, jy / r, jz / r};
+    for (int a = 0; a < Lat<Q>::D; ++a) {
+      if (!isfinite(u[a])) bad = true;
+      if (!first) dmax = fmax(dmax, fabs(u[a] - usnap[a * g.plane + cell]));
+      umax = fmax(umax, fabs(u[a]));
+      usnap[a * g.plane + cell] = u[a];
+    }
+    if (!isfinite(r)) bad = true;
+  }
+  if (bad || first) dmax = INFINITY;
+  const double a = block_max256(dmax, lds);
+  const double b = block_max256(umax, lds);
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  if (t == 0) {
+    partials[2 * linear_block()] = a;
+    partials[2 * linear_block() + 1] = b;
+  }
+}
+
+// which = 0: J of the current state; 1: window-mean J (from accumulated terms)
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_objective(const Geo g, const ObjBox ob, const S* __restrict__ A,
+                                                   const S* __restrict__ ghost, int parity,
+                                                   const typename Prec<S>::Dd* __restrict__ dpor,
+                                                   int which, const double* __restrict__ acc_obj,
+                                                   double inv, double* __restrict__ partials) {
+  using T = typename Prec<S>::T;
+  __shared__ double lds[4];
+  CELL_PROLOGUE
+  double v = 0.0;
+  int64_t r;
+  if (valid && region_index<Q>(ob, x, y, z, r)) {
+    if (which == 1) {
+      v = acc_obj[Coef<Q>::J * ob.rplane + r] * inv;
+    } else {
+      T s[Q];
+      load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+      double sd[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
+      double dr, jx, jy, jz, P[6];
+      cell_moments<Q, double>(sd, dr, jx, jy, jz);
+      neq_flux<Q, double>(sd, dr, jx, jy, jz, 1.0 / (1.0 + dr), P);
+      double terms[Coef<Q>::N];
+      objective_terms<Q>(ob, (double)dpor[cell], dr, jx, jy, jz, P, terms);
+      v = terms[Coef<Q>::J];
+    }
+  }
+  const double sum = block_sum256(v, lds);
+  if (threadIdx.x + blockDim.x * threadIdx.y == 0) partials[linear_block()] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_sum(const double* __restrict__ partials, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += partials[i];
+  const double s = block_sum256(v, lds);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_max2(const double* __restrict__ partials, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double lds[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double pa = partials[2 * i], pb = partials[2 * i + 1];
+    a = (pa != pa) ? INFINITY : fmax(a, pa);
+    b = (pb != pb) ? INFINITY : fmax(b, pb);
+  }
+  const double ra = block_max256(a, lds);
+  const double rb = block_max256(b, lds);
+  if (threadIdx.x == 0) {
+    out[0] = ra;
+    out[1] = rb;
+  }
+}
+
+// =========================================================================
+// adjoint preparation (row a7): freeze the Jacobian data at the steady or
+// window-mean state (Eqs. adjoint_steady / adjoint_unsteady)
+// =========================================================================
+
+struct PrepIn {
+  const double* acc_rho;
+  const double* acc_j;
+  const double* acc_f;
+  const double* acc_tau;
+  const double* acc_obj;
+  double inv;
+  int source;      // 0 steady (current state), 1 window mean
+  int smag, turb;  // closure present, 0 frozen / 1 differentiated
+  double tau0, tau_adj, kS;
+};
+
+template <int Q, typename S, typename SA>
+__global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox ob, const PrepIn pin,
+                                                      const S* __restrict__ A,
+                                                      const S* __restrict__ ghost, int parity,
+                                                      const typename Prec<S>::Dd* __restrict__ dpor,
+                                                      SA* __restrict__ prep, double* __restrict__ src,
+                                                      double* __restrict__ gdat,
+                                                      double* __restrict__ oprep) {
+  using L = Lat<Q>;
+  using T = typename Prec<S>::T;
+  constexpr int D = L::D;
+  CELL_PROLOGUE
+  if (!valid || (inout && x == 0)) return;
+  double fs[Q];  // shifted populations f - w of the frozen state
+  double drho, jx, jy, jz;
+  const bool need_f = (pin.source == 0) || (pin.smag && pin.turb == 1);
+  if (pin.source == 1) {
+    drho = pin.acc_rho[cell] * pin.inv;
+    jx = pin.acc_j[cell] * pin.inv;
+    jy = pin.acc_j[g.plane + cell] * pin.inv;
+    jz = (D == 3) ? pin.acc_j[2 * g.plane + cell] * pin.inv : 0.0;
+    if (need_f) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fs[k] = pin.acc_f[k * g.plane + cell] * pin.inv;
+    }
+  } else {
+    T s[Q];
+    load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) fs[k] = (double)s[k];
+    cell_moments<Q, double>(fs, drho, jx, jy, jz);
+  }
+  const double rho = 1.0 + drho, ir = 1.0 / rho;
+  const double u[3] = {jx * ir, jy * ir, jz * ir};
+  const double d = (double)dpor[cell];
+  const double ut[3] = {d * u[0], d * u[1], d * u[2]};
+  const double ta = pin.tau_adj;
+  double P[6] = {0, 0, 0, 0, 0, 0};
+  if (pin.smag && need_f) neq_flux<Q, double>(fs, drho, jx, jy, jz, ir, P);
+  double tau_used;
+  if (!pin.smag) {
+    tau_used = ta;
+  } else if (pin.turb == 1) {
+    tau_used = 0.5 * (ta + sqrt(ta * ta + pin.kS * sqrt(frob2(P))));
+  } else {
+    double tmean;
+    if (pin.source == 1)
+      tmean = pin.acc_tau[cell] * pin.inv;
+    else
+      tmean = 0.5 * (pin.tau0 + sqrt(pin.tau0 * pin.tau0 + pin.kS * sqrt(frob2(P))));
+    tau_used = ta + (tmean - pin.tau0);
+  }
+  const double omega = 1.0 / tau_used;
+
+  for (int a = 0; a < D; ++a) prep[a * g.plane + cell] = (SA)ut[a];
+  prep[D * g.plane + cell] = (SA)d;
+  prep[(D + 1) * g.plane + cell] = (SA)omega;
+  if (pin.smag && pin.turb == 1) {
+    // f^neq_j = f_j - f^eq_j(rho, d u) and the coefficients of
+    // (1/tau^2) dtau/df_i = b0 + b1.xi_i + b2:xi_i xi_i.
+    const double tt = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const double cu = L::cx[k] * ut[0] + L::cy[k] * ut[1] + L::cz[k] * ut[2];
+      const double feqs = L::w[k] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * tt));
+      prep[(D + 2 + k) * g.plane + cell] = (SA)(fs[k] - feqs);
+    }
+    const double Pn = sqrt(frob2(P));
+    double cc = 0.0;
+    if (Pn > 0.0) cc = pin.kS / (4.0 * sqrt(ta * ta + pin.kS * Pn) * Pn * tau_used * tau_used);
+    const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
+    double Pu[3], uPu = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      Pu[a] = Pm[a][0] * u[0] + Pm[a][1] * u[1] + Pm[a][2] * u[2];
+      uPu += u[a] * Pu[a];
+    }
+    const double tr = P[0] + P[1] + P[2];
+    const int64_t bo = (D + 2 + Q);
+    prep[bo * g.plane + cell] = (SA)(cc * (uPu - tr / 3.0));
+    for (int a = 0; a < D; ++a) prep[(bo + 1 + a) * g.plane + cell] = (SA)(-2.0 * cc * Pu[a]);
+    for (int m6 = 0; m6 < 6; ++m6) {
+      const int m = sym_index<Q>(m6);
+      if (m >= 0) prep[(bo + 1 + D + m) * g.plane + cell] = (SA)(cc * P[m6]);
+    }
+  }
+  gdat[cell] = rho;
+  for (int a = 0; a < D; ++a) gdat[(1 + a) * g.plane + cell] = u[a];
+  gdat[(D + 1) * g.plane + cell] = omega;
+  if (inout && x == g.nx - 1) {
+    const int64_t o = y + (int64_t)g.ny * z;
+    oprep[o] = rho;
+    for (int a = 0; a < D; ++a) oprep[(1 + a) * g.gplane + o] = u[a];
+  }
+  int64_t r;
+  if (region_index<Q>(ob, x, y, z, r)) {
+    if (pin.source == 1) {
+#pragma unroll
+      for (int m = 0; m < Coef<Q>::N; ++m) src[m * ob.rplane + r] = pin.acc_obj[m * ob.rplane + r] * pin.inv;
+    } else {
+      double Pq[6];
+      neq_flux<Q, double>(fs, drho, jx, jy, jz, ir, Pq);
+      double terms[Coef<Q>::N];
+      objective_terms<Q>(ob, d, drho, jx, jy, jz, Pq, terms);
+#pragma unroll
+      for (int m = 0; m < Coef<Q>::N; ++m) src[m * ob.rplane + r] = terms[m];
+    }
+  }
+}
+
+// =========================================================================
+// adjoint sweep (row a8): lambda_i = sum_j dC_j/df_i phi_j - dJ/df_i at each
+// cell (closed form in the weighted adjoint moments), then phi = S^T lambda
+// through the relabelled AA propagation.
+// =========================================================================
+
+struct AdjC {
+  int les;       // per-cell omega
+  int diff;      // differentiated closure term
+  double omega0;
+};
+
+// Adjoint values of a cell as read by an even step / the gradient: canonical
+// slots, with the outlet's outgoing directions zero unless bounce-back wrote them.
+template <int Q, typename SA>
+__device__ __forceinline__ void adjoint_read_canonical(const Geo& g, const SA* __restrict__ A, int x,
+                                                       int y, int z, int64_t cell, bool outlet,
+                                                       SA (&ph)[Q]) {
+  using L = Lat<Q>;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) ph[k] = A[k * g.plane + cell];
+  if (outlet) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (L::cx[k] != -1) continue;
+      int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+      if (classify(g, sx, sy, sz) != NB_BOUNCE) ph[k] = (SA)0;
+    }
+  }
+}
+
+template <int Q, typename SA, bool ODD>
+__global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, const AdjC ac,
+                                                 SA* __restrict__ A, const SA* __restrict__ prep,
+                                                 const double* __restrict__ src,
+                                                 const double* __restrict__ oprep,
+                                                 const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
+  using L = Lat<Q>;
+  using T = SA;
+  constexpr int D = L::D;
+  CELL_PROLOGUE
+  if (!valid) return;
+  if (inout && x == 0) {  // inlet: no dependence on the state, lambda = 0
+    if (!ODD) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (SA)0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, (SA)0);
+    }
+    return;
+  }
+  const bool outlet = inout && (x == g.nx - 1);
+  T ph[Q];  // phihat_k = phi_opp(k)
+  if (!ODD) {
+    adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, outlet, ph);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+      const int t = classify(g, sx, sy, sz);
+      if (t == NB_BOUNCE)
+        ph[k] = A[k * g.plane + cell];
+      else if (t == NB_OUTLET)
+        ph[k] = (T)0;
+      else
+        ph[k] = A[L::opp[k] * g.plane + cell_of(g, sx, sy, sz)];
+    }
+  }
+  // weighted moments of phi: m0 = sum w phi, m1 = sum w phi xi, m2 = sum w phi xi xi
+  T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const T wp = (T)L::w[k] * ph[k];
+    m0 += wp;
+    // phi_i = ph[opp i]; xi_opp(k) = -xi_k
+    m1x -= (T)L::cx[k] * wp;
+    m1y -= (T)L::cy[k] * wp;
+    m1z -= (T)L::cz[k] * wp;
+    mxx += (T)(L::cx[k] * L::cx[k]) * wp;
+    myy += (T)(L::cy[k] * L::cy[k]) * wp;
+    mzz += (T)(L::cz[k] * L::cz[k]) * wp;
+    mxy += (T)(L::cx[k] * L::cy[k]) * wp;
+    mxz += (T)(L::cx[k] * L::cz[k]) * wp;
+    myz += (T)(L::cy[k] * L::cz[k]) * wp;
+  }
+  const T tx = prep[cell];
+  const T ty = prep[g.plane + cell];
+  const T tz = (D == 3) ? prep[2 * g.plane + cell] : (T)0;
+  const T d = prep[D * g.plane + cell];
+  const T omega = ac.les ? prep[(D + 1) * g.plane + cell] : (T)ac.omega0;
+  const T tt = tx * tx + ty * ty + tz * tz;
+  const T m2tx = mxx * tx + mxy * ty + mxz * tz;
+  const T m2ty = mxy * tx + myy * ty + myz * tz;
+  const T m2tz = mxz * tx + myz * ty + mzz * tz;
+  const T tmt = tx * m2tx + ty * m2ty + tz * m2tz;
+  // sum_j phi_j d f^eq_j / d f_i = Phr + Phj . xi_i
+  const T Phr = m0 * ((T)1 + (T)1.5 * tt) - (T)4.5 * tmt;
+  const T Pjx = d * ((T)3 * m1x + (T)9 * m2tx - (T)3 * m0 * tx);
+  const T Pjy = d * ((T)3 * m1y + (T)9 * m2ty - (T)3 * m0 * ty);
+  const T Pjz = d * ((T)3 * m1z + (T)9 * m2tz - (T)3 * m0 * tz);
+  T lam[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    lam[i] = ((T)1 - omega) * ph[L::opp[i]] +
+             omega * (Phr + (T)L::cx[i] * Pjx + (T)L::cy[i] * Pjy + (T)L::cz[i] * Pjz);
+  if (ac.diff) {  // differentiated Smagorinsky: (sum_j phi_j f^neq_j) (1/tau^2) dtau/df_i
+    T sd = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sd += ph[k] * prep[(D + 2 + L::opp[k]) * g.plane + cell];
+    T b[Coef<Q>::NB];
+#pragma unroll
+    for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = prep[(D + 2 + Q + m) * g.plane + cell];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] += sd * quad_eval<Q, T>(b, i);
+  }
+  if (outlet) {  // virtual column: sum_j dV_j/df_i phiV_j = (xi_i - u).Psi / rho
+    const int64_t o = y + (int64_t)g.ny * z;
+    T v0 = 0, v1x = 0, v1y = 0, v1z = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (L::cx[k] != -1) continue;
+      const T wp = (T)L::w[k] * pv_in[k * g.gplane + o];
+      v0 += wp;
+      v1x += (T)L::cx[k] * wp;
+      v1y += (T)L::cy[k] * wp;
+      v1z += (T)L::cz[k] * wp;
+      vxx += (T)(L::cx[k] * L::cx[k]) * wp;
+      vyy += (T)(L::cy[k] * L::cy[k]) * wp;
+      vzz += (T)(L::cz[k] * L::cz[k]) * wp;
+      vxy += (T)(L::cx[k] * L::cy[k]) * wp;
+      vxz += (T)(L::cx[k] * L::cz[k]) * wp;
+      vyz += (T)(L::cy[k] * L::cz[k]) * wp;
+    }
+    const T ro = (T)oprep[o];
+    const T uox = (T)oprep[g.gplane + o];
+    const T uoy = (T)oprep[2 * g.gplane + o];
+    const T uoz = (D == 3) ? (T)oprep[3 * g.gplane + o] : (T)0;
+    const T Psx = (T)3 * v1x + (T)9 * (vxx * uox + vxy * uoy + vxz * uoz) - (T)3 * v0 * uox;
+    const T Psy = (T)3 * v1y + (T)9 * (vxy * uox + vyy * uoy + vyz * uoz) - (T)3 * v0 * uoy;
+    const T Psz = (T)3 * v1z + (T)9 * (vxz * uox + vyz * uoy + vzz * uoz) - (T)3 * v0 * uoz;
+    const T iro = (T)1 / ro;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      lam[i] += (((T)L::cx[i] - uox) * Psx + ((T)L::cy[i] - uoy) * Psy + ((T)L::cz[i] - uoz) * Psz) * iro;
+  }
+  int64_t r;
+  if (region_index<Q>(ob, x, y, z, r)) {
+    T a[1 + D + L::NSYM];
+#pragma unroll
+    for (int m = 0; m < 1 + D + L::NSYM; ++m) a[m] = (T)src[(Coef<Q>::A0 + m) * ob.rplane + r];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] -= quad_eval<Q, T>(a, i);
+  }
+
+  if (!ODD) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) A[i * g.plane + cell] = lam[i];
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, lam[L::opp[k]]);
+  }
+  if (outlet) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (L::cx[k] != -1) continue;
+      int vx = x, vy = y - L::cy[k], vz = z - L::cz[k];
+      if (classify(g, vx, vy, vz) != NB_CELL) continue;
+      pv_out[k * g.gplane + vy + (int64_t)g.ny * vz] = lam[k];
+    }
+  }
+}
+
+// Residual: max |phi - snapshot| and max |phi| over the state cells.
+template <int Q, typename SA>
+__global__ __launch_bounds__(256) void k_adjoint_residual(const Geo g, const SA* __restrict__ A,
+                                                          SA* __restrict__ snap, int first,
+                                                          double* __restrict__ partials) {
+  __shared__ double lds[4];
+  CELL_PROLOGUE
+  double dmax = 0.0, pmax = 0.0;
+  bool bad = false;
+  if (valid && !(inout && x == 0)) {
+    SA ph[Q];
+    adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, inout && x == g.nx - 1, ph);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const double v = (double)ph[k];
+      if (!isfinite(v)) bad = true;
+      if (!first) dmax = fmax(dmax, fabs(v - (double)snap[k * g.plane + cell]));
+      pmax = fmax(pmax, fabs(v));
+      snap[k * g.plane + cell] = ph[k];
+    }
+  }
+  if (bad || first) dmax = INFINITY;
+  const double a = block_max256(dmax, lds);
+  const double b = block_max256(pmax, lds);
+  if (threadIdx.x + blockDim.x * threadIdx.y == 0) {
+    partials[2 * linear_block()] = a;
+    partials[2 * linear_block() + 1] = b;
+  }
+}
+
+// Gradient (row a9): dJ/dd = dJ/dd|explicit - sum_i phi_i dC_i/dd, with
+// sum_i phi_i dC_i/dd = omega rho [3 m1.u + 9 d u.m2.u - 3 d m0 |u|^2].
+template <int Q, typename SA, typename Dd>
+__global__ __launch_bounds__(256) void k_gradient(const Geo g, const ObjBox ob, const SA* __restrict__ A,
+                                                  const Dd* __restrict__ dpor,
+                                                  const double* __restrict__ gdat,
+                                                  const double* __restrict__ src,
+                                                  double* __restrict__ out) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  CELL_PROLOGUE
+  if (!valid) return;
+  if (inout && x == 0) {
+    out[cell] = 0.0;
+    return;
+  }
+  SA ph[Q];
+  adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, inout && x == g.nx - 1, ph);
+  double m0 = 0, m1[3] = {0, 0, 0}, m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double wp = L::w[k] * (double)ph[k];
+    const int c[3] = {-L::cx[k], -L::cy[k], -L::cz[k]};  // direction of phi_opp(k)
+    m0 += wp;
+    for (int a = 0; a < 3; ++a) {
+      m1[a] += c[a] * wp;
+      for (int b = 0; b < 3; ++b) m2[a][b] += c[a] * c[b] * wp;
+    }
+  }
+  const double rho = gdat[cell];
+  const double u[3] = {gdat[g.plane + cell], gdat[2 * g.plane + cell],
+                       D == 3 ? gdat[3 * g.plane + cell] : 0.0};
+  const double omega = gdat[(D + 1) * g.plane + cell];
+  const double d = (double)dpor[cell];
+  double m1u = 0, um2u = 0, uu = 0;
+  for (int a = 0; a < 3; ++a) {
+    m1u += m1[a] * u[a];
+    uu += u[a] * u[a];
+    for (int b = 0; b < 3; ++b) um2u += u[a] * m2[a][b] * u[b];
+  }
+  double dJdd = 0.0;
+  int64_t r;
+  if (region_index<Q>(ob, x, y, z, r)) dJdd = src[Coef<Q>::DJDD * ob.rplane + r];
+  out[cell] = dJdd - omega * rho * (3.0 * m1u + 9.0 * d * um2u - 3.0 * d * m0 * uu);
+}
+
+// Adjoint populations in the canonical layout (phi_i on post-collision slots).
+template <int Q, typename SA>
+__global__ __launch_bounds__(256) void k_adjoint_gather(const Geo g, const SA* __restrict__ A,
+                                                        double* __restrict__ out, int64_t n) {
+  using L = Lat<Q>;
+  CELL_PROLOGUE
+  if (!valid) return;
+  if (inout && x == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i * n + cell] = 0.0;
+    return;
+  }
+  SA ph[Q];
+  adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, inout && x == g.nx - 1, ph);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i * n + cell] = (double)ph[L::opp[i]];
+}
+
+// =========================================================================
+// host launchers
+// =========================================================================
+
+Geo make_geo(const hlbm_lattice_s* L) {
+  Geo g;
+  g.nx = L->desc.nx;
+  g.ny = L->desc.ny;
+  g.nz = L->desc.nz;
+  g.bcx = L->desc.bc_x;
+  g.bcy = L->desc.bc_y;
+  g.bcz = L->desc.stencil == HLBM_D2Q9 ? BC_PERIODIC : L->desc.bc_z;
+  g.plane = L->plane;
+  g.gplane = L->gplane;
+  g.inlet_profile = L->desc.inlet_profile;
+  g.u_in = L->desc.u_in;
+  return g;
+}
+
+ObjBox make_obj(const hlbm_lattice_s* L) {
+  ObjBox o;
+  o.active = L->obj_set;
+  o.kind = L->obj_kind;
+  for (int a = 0; a < 3; ++a) {
+    o.lo[a] = L->lo[a];
+    o.rn[a] = L->rn[a];
+  }
+  o.rplane = L->rplane;
+  o.u0 = L->u0;
+  o.p0 = L->p0;
+  o.tau0 = L->desc.tau;
+  return o;
+}
+
+Coll make_coll(const hlbm_lattice_s* L) {
+  Coll c;
+  c.tau0 = L->desc.tau;
+  c.omega0 = 1.0 / L->desc.tau;
+  c.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
+  c.smag = L->desc.smagorinsky_cs > 0.0;
+  for (int a = 0; a < 3; ++a) c.force[a] = L->desc.force[a];
+  return c;
+}
+
+dim3 cell_grid(const hlbm_lattice_s* L) {
+  return dim3((L->desc.nx + BX - 1) / BX, (L->desc.ny + BY - 1) / BY, L->desc.nz);
+}
+
+static const dim3 kBlock(BX, BY, 1);
+
+template <int Q, typename S>
+static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate) {
+  using Dd = typename Prec<S>::Dd;
+  const Geo g = make_geo(L);
+  const Coll c = make_coll(L);
+  const ObjBox ob = make_obj(L);
+  Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
+          c.smag ? L->acc_tau : nullptr, L->acc_obj};
+  S* A = (S*)L->f;
+  const Dd* dp = (const Dd*)L->dpor;
+  S* gh = (S*)L->ghost;
+  const dim3 grid = cell_grid(L);
+  if (L->parity == 0) {
+    if (accumulate)
+      k_primal<Q, S, false, true><<<grid, kBlock, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+    else
+      k_primal<Q, S, false, false><<<grid, kBlock, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+  } else {
+    if (accumulate)
+      k_primal<Q, S, true, true><<<grid, kBlock, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+    else
+      k_primal<Q, S, true, false><<<grid, kBlock, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+  }
+  return hipGetLastError();
+}
+
+#define HLBM_DISPATCH(L, FN, ...)                                             \
+  do {                                                                        \
+    const int key_ = (L)->desc.stencil * 3 + (L)->desc.precision;            \
+    switch (key_) {                                                           \
+      case 0: return FN<9, double>(__VA_ARGS__);                              \
+      case 1: return FN<9, float>(__VA_ARGS__);                               \
+      case 2: return FN<9, _Float16>(__VA_ARGS__);                            \
+      case 3: return FN<19, double>(__VA_ARGS__);                             \
+      case 4: return FN<19, float>(__VA_ARGS__);                              \
+      case 5: return FN<19, _Float16>(__VA_ARGS__);                           \
+      default: return hipErrorInvalidValue;                                   \
+    }                                                                         \
+  } while (0)
+
+hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate) {
+  HLBM_DISPATCH(L, primal_impl, L, accumulate);
+}
+
+template <int Q, typename S>
+static hipError_t init_impl(hlbm_lattice_s* L, double rho0, const double* u_dev) {
+  k_init<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (S*)L->f,
+                                                       (const typename Prec<S>::Dd*)L->dpor, rho0,
+                                                       u_dev, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev) {
+  HLBM_DISPATCH(L, init_impl, L, rho0, u_dev);
+}
+
+hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
+                           const double* noise_dev, int mode, double box_half) {
+  if (L->desc.precision == HLBM_FP64)
+    k_cylinder<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, xc, yc,
+                                                               D, noise_dev, mode, box_half);
+  else
+    k_cylinder<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, xc, yc, D,
+                                                              noise_dev, mode, box_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev) {
+  if (L->desc.precision == HLBM_FP64)
+    k_set_porosity<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, d_dev,
+                                                                   bad_dev);
+  else
+    k_set_porosity<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, d_dev,
+                                                                  bad_dev);
+  return hipGetLastError();
+}
+
+template <int Q, typename S>
+static hipError_t gather_impl(hlbm_lattice_s* L, double* out) {
+  k_gather<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f,
+                                                         (const S*)L->ghost, L->parity, out, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev) { HLBM_DISPATCH(L, gather_impl, L, out_dev); }
+
+template <int Q, typename S>
+static hipError_t scatter_impl(hlbm_lattice_s* L, const double* in) {
+  k_scatter<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (S*)L->f, in, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_scatter(hlbm_lattice_s* L, const double* in_dev) {
+  HLBM_DISPATCH(L, scatter_impl, L, in_dev);
+}
+
+template <int Q, typename S>
+static hipError_t moments_impl(hlbm_lattice_s* L, double* rho, double* u) {
+  k_moments<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f,
+                                                          (const S*)L->ghost, L->parity, rho, u, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_moments(hlbm_lattice_s* L, double* rho_dev, double* u_dev) {
+  HLBM_DISPATCH(L, moments_impl, L, rho_dev, u_dev);
+}
+
+hipError_t launch_mean_fields(hlbm_lattice_s* L, int field, double* out_dev) {
+  const double inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  if (L->desc.stencil == HLBM_D2Q9)
+    k_mean_fields<9><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), field, L->acc_rho, L->acc_j,
+                                                             L->acc_tau, inv, out_dev, L->n);
+  else
+    k_mean_fields<19><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), field, L->acc_rho, L->acc_j,
+                                                              L->acc_tau, inv, out_dev, L->n);
+  return hipGetLastError();
+}
+
+static int grid_blocks(const dim3& g) { return (int)(g.x * g.y * g.z); }
+
+template <int Q, typename S>
+static hipError_t steady_impl(hlbm_lattice_s* L, int first, double* partials, int* nb) {
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  k_steady_check<Q, S><<<grid, kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f, (const S*)L->ghost,
+                                                       L->parity, L->usnap, first, partials);
+  return hipGetLastError();
+}
+hipError_t launch_steady_check(hlbm_lattice_s* L, int first, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, steady_impl, L, first, partials, nblocks);
+}
+
+template <int Q, typename S>
+static hipError_t objective_impl(hlbm_lattice_s* L, int which, double* partials, int* nb) {
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  const double inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  k_objective<Q, S><<<grid, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+                                                    (const S*)L->ghost, L->parity,
+                                                    (const typename Prec<S>::Dd*)L->dpor, which,
+                                                    L->acc_obj, inv, partials);
+  return hipGetLastError();
+}
+hipError_t launch_objective(hlbm_lattice_s* L, int which, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, objective_impl, L, which, partials, nblocks);
+}
+
+hipError_t launch_finalize_sum(hlbm_lattice_s* L, const double* partials, int n, double* out) {
+  k_finalize_sum<<<1, 256, 0, L->stream>>>(partials, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_max2(hlbm_lattice_s* L, const double* partials, int n, double* out) {
+  k_finalize_max2<<<1, 256, 0, L->stream>>>(partials, n, out);
+  return hipGetLastError();
+}
+
+// adjoint storage type: FP64 form -> double, FP32/FP16S forms -> float
+template <typename S>
+struct AdjT {
+  using type = float;
+};
+template <>
+struct AdjT<double> {
+  using type = double;
+};
+
+template <int Q, typename S>
+static hipError_t prep_impl(hlbm_lattice_s* L, int source, double tau_adj, int turb) {
+  using SA = typename AdjT<S>::type;
+  PrepIn pin;
+  pin.acc_rho = L->acc_rho;
+  pin.acc_j = L->acc_j;
+  pin.acc_f = L->acc_f;
+  pin.acc_tau = L->acc_tau;
+  pin.acc_obj = L->acc_obj;
+  pin.inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  pin.source = source;
+  pin.smag = L->desc.smagorinsky_cs > 0.0;
+  pin.turb = turb;
+  pin.tau0 = L->desc.tau;
+  pin.tau_adj = tau_adj;
+  pin.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
+  k_adjoint_prep<Q, S, SA><<<cell_grid(L), kBlock, 0, L->stream>>>(
+      make_geo(L), make_obj(L), pin, (const S*)L->f, (const S*)L->ghost, L->parity,
+      (const typename Prec<S>::Dd*)L->dpor, (SA*)L->prep, L->src, L->gdat, L->oprep);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_prep(hlbm_lattice_s* L, int source, double tau_adj, int turb) {
+  HLBM_DISPATCH(L, prep_impl, L, source, tau_adj, turb);
+}
+
+template <int Q, typename S>
+static hipError_t adjoint_impl(hlbm_lattice_s* L) {
+  using SA = typename AdjT<S>::type;
+  AdjC ac;
+  ac.les = L->adj_les;
+  ac.diff = L->adj_diff;
+  ac.omega0 = L->adj_omega;  // used when the relaxation time is uniform (no closure)
+  const Geo g = make_geo(L);
+  const ObjBox ob = make_obj(L);
+  SA* A = (SA*)L->phi;
+  const SA* pin = (const SA*)L->pv[L->pvcur];
+  SA* pout = (SA*)L->pv[L->pvcur ^ 1];
+  if ((L->adj_iters & 1) == 0)
+    k_adjoint<Q, SA, false><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, ac, A, (const SA*)L->prep, L->src,
+                                                                   L->oprep, pin, pout);
+  else
+    k_adjoint<Q, SA, true><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, ac, A, (const SA*)L->prep, L->src,
+                                                                  L->oprep, pin, pout);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_step(hlbm_lattice_s* L) { HLBM_DISPATCH(L, adjoint_impl, L); }
+
+template <int Q, typename S>
+static hipError_t residual_impl(hlbm_lattice_s* L, int first, double* partials, int* nb) {
+  using SA = typename AdjT<S>::type;
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  k_adjoint_residual<Q, SA><<<grid, kBlock, 0, L->stream>>>(make_geo(L), (const SA*)L->phi, (SA*)L->snap,
+                                                            first, partials);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, residual_impl, L, first, partials, nblocks);
+}
+
+template <int Q, typename S>
+static hipError_t gradient_impl(hlbm_lattice_s* L, double* g_dev) {
+  using SA = typename AdjT<S>::type;
+  k_gradient<Q, SA, typename Prec<S>::Dd><<<cell_grid(L), kBlock, 0, L->stream>>>(
+      make_geo(L), make_obj(L), (const SA*)L->phi, (const typename Prec<S>::Dd*)L->dpor, L->gdat, L->src,
+      g_dev);
+  return hipGetLastError();
+}
+hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev) { HLBM_DISPATCH(L, gradient_impl, L, g_dev); }
+
+template <int Q, typename S>
+static hipError_t adjoint_gather_impl(hlbm_lattice_s* L, double* out) {
+  using SA = typename AdjT<S>::type;
+  k_adjoint_gather<Q, SA><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const SA*)L->phi, out, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev) {
+  HLBM_DISPATCH(L, adjoint_gather_impl, L, out_dev);
+}
+
+}  // namespace hlbm

@@ -1,0 +1,324 @@
+"""ctypes binding of libhlbm.so (the gfx950 HLBM mean-flow adjoint library).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Arrays may be numpy arrays (host memory) or torch tensors on the
+GPU (device memory, passed by data_ptr()); all exchanged values are float64.
+If the library is missing this module raises at import of the library, it
+never falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhlbm.so")
+
+D2Q9, D3Q19 = 0, 1
+FP64, FP32, FP16S = 0, 1, 2
+BC_PERIODIC, BC_WALLS, BC_INLET_OUTLET = 0, 1, 2
+INLET_UNIFORM, INLET_PARABOLIC = 1, 2
+OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM = 0, 1, 2
+TURB_FROZEN, TURB_DIFFERENTIATED = 0, 1
+SOURCE_STEADY, SOURCE_MEAN = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+NOISE_NONE, NOISE_RIM, NOISE_BOX = 0, 1, 2
+FIELD_RHO, FIELD_U, FIELD_MEAN_RHO, FIELD_MEAN_U, FIELD_POROSITY, FIELD_MEAN_TAU = range(6)
+
+OK, W_NOT_CONVERGED = 0, 1
+E_INVALID, E_OOM, E_STATE, E_DIVERGED, E_DEVICE = -1, -2, -3, -4, -5
+
+EXPORTS = [
+    "hlbm_create", "hlbm_destroy", "hlbm_footprint_bytes", "hlbm_set_porosity",
+    "hlbm_build_cylinder", "hlbm_init_equilibrium", "hlbm_set_populations",
+    "hlbm_get_populations", "hlbm_set_objective", "hlbm_run_primal", "hlbm_window_reset",
+    "hlbm_window_count", "hlbm_get_objective", "hlbm_solve_adjoint", "hlbm_get_gradient",
+    "hlbm_get_adjoint", "hlbm_get_field", "hlbm_synchronize", "hlbm_profile_enable",
+    "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
+]
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("stencil", C.c_int32),
+        ("precision", C.c_int32),
+        ("nx", C.c_int32),
+        ("ny", C.c_int32),
+        ("nz", C.c_int32),
+        ("tau", C.c_double),
+        ("smagorinsky_cs", C.c_double),
+        ("bc_x", C.c_int32),
+        ("bc_y", C.c_int32),
+        ("bc_z", C.c_int32),
+        ("inlet_profile", C.c_int32),
+        ("u_in", C.c_double),
+        ("force", C.c_double * 3),
+        ("track_mean_populations", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class AdjointOpts(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("source", C.c_int32),
+        ("tau_adj", C.c_double),
+        ("turb", C.c_int32),
+        ("max_iters", C.c_int64),
+        ("tol", C.c_double),
+        ("check_every", C.c_int64),
+        ("restart", C.c_int32),
+    ]
+
+
+class AdjointReport(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("residual", C.c_double)]
+
+
+class HlbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libhlbm.so; raises if it is not built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
+                          "python paper_2606_31707_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "hlbm_create": (i32, [P(Desc), P(vp)]),
+        "hlbm_destroy": (None, [vp]),
+        "hlbm_footprint_bytes": (i32, [P(Desc), i32, i32, P(C.c_uint64)]),
+        "hlbm_set_porosity": (i32, [vp, vp, i64, i32]),
+        "hlbm_build_cylinder": (i32, [vp, dbl, dbl, dbl, vp, i64, i32, i32, dbl]),
+        "hlbm_init_equilibrium": (i32, [vp, dbl, vp, i64, i32]),
+        "hlbm_set_populations": (i32, [vp, vp, i64, i32]),
+        "hlbm_get_populations": (i32, [vp, vp, i64, i32]),
+        "hlbm_set_objective": (i32, [vp, i32, P(i32), P(i32), dbl, dbl]),
+        "hlbm_run_primal": (i32, [vp, i64, i32, dbl, i64, P(i64)]),
+        "hlbm_window_reset": (i32, [vp]),
+        "hlbm_window_count": (i32, [vp, P(i64)]),
+        "hlbm_get_objective": (i32, [vp, i32, P(dbl)]),
+        "hlbm_solve_adjoint": (i32, [vp, P(AdjointOpts), P(AdjointReport)]),
+        "hlbm_get_gradient": (i32, [vp, vp, i64, i32]),
+        "hlbm_get_adjoint": (i32, [vp, vp, i64, i32]),
+        "hlbm_get_field": (i32, [vp, i32, vp, i64, i32]),
+        "hlbm_synchronize": (i32, [vp]),
+        "hlbm_profile_enable": (i32, [vp, i32]),
+        "hlbm_profile_get": (i32, [vp, P(dbl), P(i64), P(dbl), P(i64)]),
+        "hlbm_bytes_per_update": (i32, [vp, P(dbl), P(dbl), P(dbl)]),
+        "hlbm_status_string": (C.c_char_p, [i32]),
+        "hlbm_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(OK,)) -> int:
+    if status in allow:
+        return status
+    lib = load_library()
+    raise HlbmError(status, f"{lib.hlbm_status_string(status).decode()}: {lib.hlbm_last_error().decode()}")
+
+
+def _arr_in(a, n):
+    """(pointer, count, mem, keepalive) for an input array."""
+    if a is None:
+        return None, 0, MEM_HOST, None
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):  # torch tensor
+        import torch
+        t = a.detach()
+        if t.dtype != torch.float64:
+            t = t.to(torch.float64)
+        t = t.contiguous()
+        if t.is_cuda:
+            return C.c_void_p(t.data_ptr()), t.numel(), MEM_DEVICE, t
+        a = t.numpy()
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())
+    return arr.ctypes.data_as(C.c_void_p), arr.size, MEM_HOST, arr
+
+
+def _out(out, n):
+    """(pointer, mem, array) for an output buffer (numpy allocated if None)."""
+    if out is None:
+        arr = np.empty(n, dtype=np.float64)
+        return arr.ctypes.data_as(C.c_void_p), MEM_HOST, arr
+    if hasattr(out, "data_ptr") and getattr(out, "is_cuda", False):
+        import torch
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == n
+        return C.c_void_p(out.data_ptr()), MEM_DEVICE, out
+    assert isinstance(out, np.ndarray) and out.dtype == np.float64 and out.flags.c_contiguous and out.size == n
+    return out.ctypes.data_as(C.c_void_p), MEM_HOST, out
+
+
+def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
+              bc_x=BC_INLET_OUTLET, bc_y=BC_WALLS, bc_z=BC_PERIODIC,
+              inlet_profile=INLET_PARABOLIC, u_in=0.03, force=(0.0, 0.0, 0.0),
+              track_mean_populations=False, stream=None) -> Desc:
+    d = Desc()
+    d.struct_size = C.sizeof(Desc)
+    d.stencil, d.precision = stencil, precision
+    d.nx, d.ny, d.nz = nx, ny, nz
+    d.tau, d.smagorinsky_cs = tau, cs
+    d.bc_x, d.bc_y, d.bc_z = bc_x, bc_y, bc_z
+    d.inlet_profile, d.u_in = inlet_profile, u_in
+    d.force = (C.c_double * 3)(*force)
+    d.track_mean_populations = int(bool(track_mean_populations))
+    d.stream = stream
+    return d
+
+
+def footprint_bytes(desc: Desc, with_window=True, with_adjoint=True) -> int:
+    lib = load_library()
+    out = C.c_uint64()
+    _check(lib.hlbm_footprint_bytes(C.byref(desc), int(with_window), int(with_adjoint), C.byref(out)))
+    return int(out.value)
+
+
+class Lattice:
+    """One lattice on the GPU (owns an hlbm_lattice handle)."""
+
+    def __init__(self, desc: Desc | None = None, **kw):
+        self._lib = load_library()
+        self.desc = desc if desc is not None else make_desc(**kw)
+        h = C.c_void_p()
+        _check(self._lib.hlbm_create(C.byref(self.desc), C.byref(h)))
+        self._h = h
+        self.q = 9 if self.desc.stencil == D2Q9 else 19
+        self.n = self.desc.nx * self.desc.ny * self.desc.nz
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.hlbm_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- geometry / state
+    def set_porosity(self, d):
+        p, n, mem, _keep = _arr_in(d, self.n)
+        _check(self._lib.hlbm_set_porosity(self._h, p, n, mem))
+
+    def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0):
+        p, n, mem, _keep = _arr_in(noise, self.n)
+        _check(self._lib.hlbm_build_cylinder(self._h, xc, yc, D, p, n if noise is not None else 0,
+                                             mem, noise_mode, box_half))
+
+    def init_equilibrium(self, rho0=1.0, u=None):
+        p, n, mem, _keep = _arr_in(u, 3 * self.n)
+        _check(self._lib.hlbm_init_equilibrium(self._h, rho0, p, n, mem))
+
+    def set_populations(self, f):
+        p, n, mem, _keep = _arr_in(f, self.q * self.n)
+        _check(self._lib.hlbm_set_populations(self._h, p, n, mem))
+
+    def populations(self, out=None):
+        p, mem, arr = _out(out, self.q * self.n)
+        _check(self._lib.hlbm_get_populations(self._h, p, self.q * self.n, mem))
+        return arr.reshape(self.q, self.n) if isinstance(arr, np.ndarray) else arr
+
+    def porosity(self):
+        return self.field(FIELD_POROSITY)
+
+    def field(self, which, out=None):
+        n = 3 * self.n if which in (FIELD_U, FIELD_MEAN_U) else self.n
+        p, mem, arr = _out(out, n)
+        _check(self._lib.hlbm_get_field(self._h, which, p, n, mem))
+        if isinstance(arr, np.ndarray) and n == 3 * self.n:
+            return arr.reshape(3, self.n)
+        return arr
+
+    def moments(self):
+        return self.field(FIELD_RHO), self.field(FIELD_U)
+
+    # ---- objective / primal / window
+    def set_objective(self, kind, lo, hi, u0=0.0, p0=1.0 / 3.0):
+        lo3 = (C.c_int32 * 3)(*(list(lo) + [0] * (3 - len(lo))))
+        hi3 = (C.c_int32 * 3)(*(list(hi) + [0] * (3 - len(hi))))
+        _check(self._lib.hlbm_set_objective(self._h, kind, lo3, hi3, u0, p0))
+
+    def run_primal(self, n_steps, accumulate=False, steady_tol=0.0, check_every=100):
+        done = C.c_int64()
+        st = self._lib.hlbm_run_primal(self._h, int(n_steps), int(bool(accumulate)), steady_tol,
+                                       int(check_every), C.byref(done))
+        _check(st, allow=(OK, W_NOT_CONVERGED))
+        return int(done.value)
+
+    def step(self, n=1, accumulate=False):
+        return self.run_primal(n, accumulate)
+
+    def window_reset(self):
+        _check(self._lib.hlbm_window_reset(self._h))
+
+    def window_count(self) -> int:
+        c = C.c_int64()
+        _check(self._lib.hlbm_window_count(self._h, C.byref(c)))
+        return int(c.value)
+
+    def objective(self, which=0) -> float:
+        J = C.c_double()
+        _check(self._lib.hlbm_get_objective(self._h, which, C.byref(J)))
+        return J.value
+
+    def window_objective(self) -> float:
+        return self.objective(1)
+
+    # ---- adjoint / gradient
+    def solve_adjoint(self, source=SOURCE_STEADY, tau_adj=0.0, turb=TURB_DIFFERENTIATED,
+                      max_iters=1000, tol=0.0, check_every=100, restart=True):
+        o = AdjointOpts()
+        o.struct_size = C.sizeof(AdjointOpts)
+        o.source, o.tau_adj, o.turb = source, tau_adj, turb
+        o.max_iters, o.tol, o.check_every, o.restart = int(max_iters), tol, int(check_every), int(bool(restart))
+        rep = AdjointReport()
+        st = self._lib.hlbm_solve_adjoint(self._h, C.byref(o), C.byref(rep))
+        _check(st, allow=(OK, W_NOT_CONVERGED))
+        return int(rep.iters), float(rep.residual), st
+
+    def gradient(self, out=None):
+        p, mem, arr = _out(out, self.n)
+        _check(self._lib.hlbm_get_gradient(self._h, p, self.n, mem))
+        return arr
+
+    def adjoint(self, out=None):
+        p, mem, arr = _out(out, self.q * self.n)
+        _check(self._lib.hlbm_get_adjoint(self._h, p, self.q * self.n, mem))
+        return arr.reshape(self.q, self.n) if isinstance(arr, np.ndarray) else arr
+
+    # ---- timing
+    def synchronize(self):
+        _check(self._lib.hlbm_synchronize(self._h))
+
+    def profile_enable(self, on=True):
+        _check(self._lib.hlbm_profile_enable(self._h, int(bool(on))))
+
+    def profile(self):
+        pm, am = C.c_double(), C.c_double()
+        pl, al = C.c_int64(), C.c_int64()
+        _check(self._lib.hlbm_profile_get(self._h, C.byref(pm), C.byref(pl), C.byref(am), C.byref(al)))
+        return {"primal_ms": pm.value, "primal_launches": pl.value,
+                "adjoint_ms": am.value, "adjoint_launches": al.value}
+
+    def bytes_per_update(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(self._lib.hlbm_bytes_per_update(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"primal": a.value, "primal_window": b.value, "adjoint": c.value}

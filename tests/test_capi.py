@@ -1,0 +1,83 @@
+"""CPU checks of the C ABI: the library loads without a GPU and exports every
+function include/hlbm.h declares, with matching struct sizes."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hlbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hlbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["hlbm_create", "hlbm_destroy", "hlbm_set_porosity", "hlbm_build_cylinder",
+                 "hlbm_set_objective", "hlbm_run_primal", "hlbm_solve_adjoint",
+                 "hlbm_get_objective", "hlbm_get_gradient"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_31707_amd import hlbm as H
+    lib = H.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(H.EXPORTS) == declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", H.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (hlbm_[a-z_]+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layouts_match_header():
+    """Compiles a tiny C program against the header and compares sizeof/offsets
+    with the ctypes mirrors."""
+    from paper_2606_31707_amd import hlbm as H
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "hlbm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(hlbm_desc), offsetof(hlbm_desc, force),
+         offsetof(hlbm_desc, stream), sizeof(hlbm_adjoint_opts), offsetof(hlbm_adjoint_opts, restart),
+         sizeof(hlbm_adjoint_report));
+  return 0;
+}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        cpath = os.path.join(td, "t.c")
+        open(cpath, "w").write(src)
+        exe = os.path.join(td, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe], check=True)
+        vals = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
+    assert vals == [C.sizeof(H.Desc), H.Desc.force.offset, H.Desc.stream.offset, C.sizeof(H.AdjointOpts),
+                    H.AdjointOpts.restart.offset, C.sizeof(H.AdjointReport)]
+
+
+def test_status_strings_without_gpu():
+    from paper_2606_31707_amd import hlbm as H
+    lib = H.load_library()
+    assert lib.hlbm_status_string(H.E_STATE) == b"call order violated"
+    d = H.make_desc(nx=1, ny=1)
+    with pytest.raises(H.HlbmError):
+        H.footprint_bytes(d)
+    d = H.make_desc(nx=220, ny=41)
+    assert H.footprint_bytes(d, False, False) >= 220 * 41 * (9 * 8 + 8)
+
+
+def test_product_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2606_31707_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, flags=re.M), f
+                assert "hlbm_oracle" not in text, f
