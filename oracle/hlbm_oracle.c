@@ -145,17 +145,21 @@ void orc_equilibrium(int stencil, double rho, const double* v, double* feq) {
 }
 
 /* Non-equilibrium momentum flux with respect to f^eq(rho, u):
- * Pi_ab = sum_i xi_ia xi_ib f_i - rho/3 delta_ab - j_a j_b / rho. */
+ * Pi_ab = sum_i xi_ia xi_ib f_i - rho/3 delta_ab - j_a j_b / rho.
+ * Evaluated as sum_i xi_ia xi_ib (f_i - w_i) - (rho - 1)/3 delta_ab - j_a j_b / rho,
+ * the same number by sum_i w_i = 1 and sum_i w_i xi_ia xi_ib = delta_ab / 3,
+ * without cancelling two O(1/3) terms. */
 static void neq_flux(const stencil_t* s, const double* f, double Pi[3][3]) {
-  double rho, j[3];
+  double rho, j[3], drho = 0.0;
   moments(s, f, &rho, j);
+  for (int i = 0; i < s->q; ++i) drho += f[i] - s->w[i];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) Pi[a][b] = 0.0;
   for (int a = 0; a < s->dim; ++a)
     for (int b = 0; b < s->dim; ++b) {
       double m = 0.0;
-      for (int i = 0; i < s->q; ++i) m += s->c[i][a] * s->c[i][b] * f[i];
-      Pi[a][b] = m - (a == b ? rho / 3.0 : 0.0) - j[a] * j[b] / rho;
+      for (int i = 0; i < s->q; ++i) m += s->c[i][a] * s->c[i][b] * (f[i] - s->w[i]);
+      Pi[a][b] = m - (a == b ? drho / 3.0 : 0.0) - j[a] * j[b] / rho;
     }
 }
 

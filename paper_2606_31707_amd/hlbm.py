@@ -95,6 +95,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
                           "python paper_2606_31707_amd/build.py")
+    # PyTorch ships its own HIP runtime; loading it first makes libhlbm.so bind
+    # to that same runtime (same soname), so device pointers and streams are
+    # shared with torch instead of two runtimes competing for the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER

@@ -94,6 +94,22 @@ def rel_err(a, b, mask=None) -> float:
     return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
 
 
+def objective_tol(L: O.Lattice, s: Spec, kind, lo, hi, u0, rel=1e-12) -> float:
+    """Absolute tolerance for J: the first-order effect of population errors
+    of rel * max|f| on J, i.e. rel * max|f| * sum over the region of
+    sum_i |dJ_x/df_i| (J is often a small difference of O(u^2) terms)."""
+    f = L.populations()
+    d = L.porosity()
+    fmax = np.abs(f).max()
+    acc = 0.0
+    for z in range(lo[2], hi[2] + 1):
+        for y in range(lo[1], hi[1] + 1):
+            for x in range(lo[0], hi[0] + 1):
+                c = x + s.nx * (y + s.ny * z)
+                acc += np.abs(O.dJdf_cell(s.stencil, kind, f[:, c], d[c], s.tau, u0)).sum()
+    return rel * fmax * max(acc, 1e-300) + 1e-18
+
+
 def say(*a):
     """Names the case on stdout before a GPU step (survives a crash)."""
     print(*a, flush=True)
