@@ -39,6 +39,17 @@ hlbm_status fail(hlbm_status s, const char* fmt, ...) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Plane stride in elements: a multiple of 256 B, and an odd number of 256 B
+// blocks so that the q planes do not start on the same memory channel (power-
+// of-two strides measured up to 8% slower on the D3Q19 sweeps).
+int64_t plane_stride(int64_t n, size_t ssize) {
+  if (ssize == 0 || ssize > 256) return -1;
+  const int64_t unit = 256 / (int64_t)ssize;
+  int64_t m = (n + unit - 1) / unit;
+  if (m % 2 == 0) m += 1;
+  return m * unit < round_up(n, 128) ? round_up(n, 128) : m * unit;
+}
+
 hlbm_status dev_alloc(void** p, size_t bytes) {
   if (*p) return HLBM_OK;
   hipError_t e = hipMalloc(p, bytes ? bytes : 256);
@@ -206,7 +217,7 @@ hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int wit
   if (!bytes) return fail(HLBM_E_INVALID, "null output");
   const int q = q_of(desc->stencil), dim = dim_of(desc->stencil);
   const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
-  const int64_t P = round_up(n, 128), G = round_up((int64_t)desc->ny * desc->nz, 128);
+  const int64_t P = plane_stride(n, ssize_of(desc->precision)), G = round_up((int64_t)desc->ny * desc->nz, 128);
   uint64_t b = (uint64_t)P * (q * ssize_of(desc->precision) + dsize_of(desc->precision)) +
                (uint64_t)G * q * ssize_of(desc->precision);
   if (with_window) {
@@ -238,11 +249,17 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
   L->ncoef = ncoef_of(desc->stencil);
   L->nb = nb_of(desc->stencil);
   L->n = (int64_t)desc->nx * desc->ny * desc->nz;
-  L->plane = round_up(L->n, 128);
-  L->gplane = round_up((int64_t)desc->ny * desc->nz, 128);
   L->ssize = ssize_of(desc->precision);
   L->dsize = dsize_of(desc->precision);
   L->asize = asize_of(desc->precision);
+  L->plane = plane_stride(L->n, L->ssize);
+  L->gplane = round_up((int64_t)desc->ny * desc->nz, 128);
+  // every kernel indexes plane k at k * plane + cell with cell < n
+  if (L->plane < L->n || L->gplane < (int64_t)desc->ny * desc->nz) {
+    const long long pl = (long long)L->plane, nn = (long long)L->n;
+    delete L;
+    return fail(HLBM_E_INVALID, "internal: plane stride %lld < %lld cells", pl, nn);
+  }
   L->stream = (hipStream_t)desc->stream;
   auto bail = [&](hlbm_status st) {
     hlbm_destroy(L);
