@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: whole-path throughput of the HLBM mean-flow adjoint on one GPU.
 
-One step = one gradient query of the workload: porosity field build (a1),
-equilibrium initialisation (a2), the primal sweep with its FP64 window over
-the last shedding periods (a3-a6), adjoint preparation (a7), the adjoint
-sweep to a steady state (a8) and the gradient assembly (a9).  `value` is
-primal plus adjoint lattice updates per second of the whole query (MLUPS),
-inputs resident on the device.  Prints one JSON line.
+One step = one gradient query of the vortex-shedding workload (2D channel
+1100 x 410, porous cylinder D = 40 with seeded rim noise, Re = 100, FP64):
+porosity build (a1), equilibrium initialisation (a2), 200 000 primal steps
+(a3, a4) whose last ten shedding periods form the FP64 window (a5, a6; the
+period is measured from an on-device velocity probe behind the cylinder),
+adjoint preparation on the mean flow (a7), the adjoint sweep to a steady state
+(a8) and the gradient assembly for the dissipation objective (a9).
+
+`value` = (primal + adjoint lattice updates) / wall time of the whole query,
+in MLUPS, inputs resident on the device.  Prints one JSON line; progress goes
+to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,57 +31,74 @@ from paper_2606_31707_amd import hlbm as H  # noqa: E402
 from paper_2606_31707_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2606_31707_amd", "csrc", "hlbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_primal_d2q9_fp64_vortex_re100_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_lattice(w: I.Workload, precision: int) -> H.Lattice:
-    return H.Lattice(stencil=w.stencil, precision=precision, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
-                     bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
-                     u_in=w.u_max, track_mean_populations=False)
+def shedding_period(uy: np.ndarray):
+    """Median spacing of upward zero crossings of u_y - mean over the last
+    half of the record (None if fewer than three crossings)."""
+    s = uy[len(uy) // 2:]
+    if len(s) < 16:
+        return None
+    s = s - s.mean()
+    if np.abs(s).max() < 1e-7:
+        return None
+    i = np.nonzero((s[:-1] < 0) & (s[1:] >= 0))[0]
+    if len(i) < 3:
+        return None
+    t = i + s[i] / (s[i] - s[i + 1])  # linear interpolation of the crossing
+    return float(np.median(np.diff(t)))
 
 
 class Query:
-    """One gradient query on a resident lattice."""
+    """One gradient query on a resident lattice (the lattice is reused)."""
 
-    def __init__(self, w: I.Workload, precision: int, primal_steps: int, window_steps: int,
-                 adj_max: int, adj_tol: float, adj_check: int):
+    def __init__(self, w: I.Workload, precision: int, primal_steps: int, adj_max: int, adj_tol: float,
+                 adj_check: int, periods: int):
         self.w = w
-        self.G = make_lattice(w, precision)
+        self.G = H.Lattice(stencil=w.stencil, precision=precision, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau,
+                           cs=w.cs, bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z,
+                           inlet_profile=w.inlet_profile, u_in=w.u_max)
         self.noise = I.porosity_noise(w)
-        self.primal_steps = primal_steps
-        self.window_steps = window_steps
+        self.T = primal_steps
+        self.W_max = primal_steps // 2
+        self.periods = periods
         self.adj_max, self.adj_tol, self.adj_check = adj_max, adj_tol, adj_check
         self.G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
-        self.grad = None
 
     def run(self):
         w, G = self.w, self.G
         G.build_cylinder(w.xc, w.yc, w.D, noise=self.noise, noise_mode=w.noise_mode, box_half=w.box_half)
         G.init_equilibrium(1.0, I.initial_velocity(w))
-        G.run_primal(self.primal_steps - self.window_steps)
-        G.run_primal(self.window_steps, accumulate=True)
-        it, res, _ = G.solve_adjoint(H.SOURCE_MEAN, max_iters=self.adj_max, tol=self.adj_tol,
-                                     check_every=self.adj_check)
+        G.set_probe(*self._probe_xyz(), self.T)
+        G.run_primal(self.T - self.W_max)
+        P = shedding_period(G.probe())
+        if P is not None and self.periods * P <= self.W_max:
+            W = int(round(self.periods * P))
+        else:  # no developed shedding yet: the last 20 % of the run
+            W = self.T // 5
+        G.run_primal(self.W_max - W)
+        G.run_primal(W, accumulate=True)
+        it, res, st = G.solve_adjoint(H.SOURCE_MEAN, max_iters=self.adj_max, tol=self.adj_tol,
+                                      check_every=self.adj_check)
         self.grad = G.gradient()
-        self.adj_iters, self.adj_res = it, res
-        return self.primal_steps * w.n + it * w.n
+        self.J = G.window_objective()
+        self.period, self.window, self.adj_iters, self.adj_res = P, W, it, res
+        return self.T * w.n + it * w.n
 
-
-def roofline(G: H.Lattice, n: int, launches: int, accumulate: bool = False):
-    G.profile_enable(True)
-    G.run_primal(launches, accumulate=accumulate)
-    prof = G.profile()
-    G.profile_enable(False)
-    avg_ms = prof["primal_ms"] / prof["primal_launches"]
-    bpu = G.bytes_per_update()["primal_window" if accumulate else "primal"]
-    achieved = bpu * n / (avg_ms * 1e-3) / 1e9
-    return avg_ms, bpu, achieved
+    def _probe_xyz(self):
+        px, py = self.w.extra.get("probe", (int(self.w.xc + 2 * self.w.D), int(self.w.yc)))
+        return px, py, 0
 
 
 def cpu_baseline(w: I.Workload, primal_steps: int, adj_iters: int):
+    """The FP64 oracle (test infrastructure) on a bounded sample of the same
+    workload, timed on the host cores."""
     import oracle as O
     p = O.Params(stencil=w.stencil, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs, bc_x=O.BC_INLET_OUTLET,
                  bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile, u_in=w.u_max)
@@ -93,10 +116,22 @@ def cpu_baseline(w: I.Workload, primal_steps: int, adj_iters: int):
     L.gradient()
     dt = time.perf_counter() - t0
     lu = (primal_steps + adj_iters) * w.n
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     return {"value": lu / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{w.name}: {primal_steps} primal steps with window sampling + adjoint preparation + "
-                      f"{adj_iters} adjoint iterations + gradient, {dt:.1f} s"}
+            "sample": f"{w.name}: {primal_steps} primal steps each with a window sample, adjoint "
+                      f"preparation, {adj_iters} adjoint iterations and the gradient ({dt:.1f} s of CPU)"}
+
+
+def traffic_for(kernel_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -104,48 +139,55 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "fp16s"], default="fp64")
     ap.add_argument("--primal-steps", type=int, default=None)
-    ap.add_argument("--window-steps", type=int, default=None)
-    ap.add_argument("--adjoint-max", type=int, default=100000)
+    ap.add_argument("--periods", type=int, default=10)
+    ap.add_argument("--adjoint-max", type=int, default=60000)
     ap.add_argument("--adjoint-tol", type=float, default=1e-6)
-    ap.add_argument("--roofline-launches", type=int, default=2000)
-    ap.add_argument("--cpu-primal", type=int, default=60)
-    ap.add_argument("--cpu-adjoint", type=int, default=60)
+    ap.add_argument("--profile-every", type=int, default=50)
+    ap.add_argument("--cpu-primal", type=int, default=40)
+    ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is in "
+              "DESIGN.md); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    prec = {"fp64": H.FP64, "fp32": H.FP32, "fp16s": H.FP16S}[args.precision]
     w = I.vortex_re100()
-    primal = args.primal_steps or w.primal_steps
-    window = args.window_steps or primal // 5
-    q = Query(w, prec, primal, window, args.adjoint_max, args.adjoint_tol, 1000)
-
+    T = args.primal_steps or w.primal_steps
+    q = Query(w, H.FP64, T, args.adjoint_max, args.adjoint_tol, 1000, args.periods)
     for i in range(args.warmup):
         t = time.perf_counter()
         q.run()
-        log(f"warmup {i}: {time.perf_counter() - t:.2f} s, adjoint iters {q.adj_iters}, residual {q.adj_res:.2e}")
+        log(f"warmup {i}: {time.perf_counter() - t:.2f} s; period {q.period}, window {q.window}, "
+            f"adjoint {q.adj_iters} it, residual {q.adj_res:.2e}")
+
+    q.G.profile_enable(args.profile_every)
     q.G.synchronize()
     t0 = time.perf_counter()
     lu = 0
     for i in range(args.steps):
         lu += q.run()
-        log(f"step {i}: adjoint iters {q.adj_iters}, residual {q.adj_res:.2e}")
+        log(f"step {i}: period {q.period}, window {q.window}, J {q.J:.6e}, adjoint {q.adj_iters} it, "
+            f"residual {q.adj_res:.2e}")
     q.G.synchronize()
     dt = time.perf_counter() - t0
+    prof = q.G.profile()
+    q.G.profile_enable(0)
 
+    bpu = q.G.bytes_per_update()
     n = w.n
-    avg_ms, bpu, achieved = roofline(q.G, n, args.roofline_launches)
-    log(f"primal sweep: {avg_ms * 1e3:.2f} us/launch, {bpu:.0f} B/LU, {achieved:.0f} GB/s, "
-        f"{n / (avg_ms * 1e-3) / 1e9:.2f} GLUPS")
+    kus = prof["primal"]["mean_us"]
+    achieved = bpu["primal"] * n / (kus * 1e-6) / 1e9
+    khash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    log(f"k_primal: {kus:.2f} us/launch ({prof['primal']['sampled']} sampled), {achieved:.0f} GB/s; "
+        f"window {prof['primal_window']['mean_us']:.2f} us; adjoint {prof['adjoint']['mean_us']:.2f} us")
+
     out = {
-        "metric": "primal+adjoint MLUPS (whole gradient query)",
+        "metric": "primal+adjoint MLUPS (whole mean-flow gradient query)",
         "value": lu / dt / 1e6,
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -155,16 +197,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32"}[args.precision],
+        "dtype": "f64",
         "data": "synthetic (seeded porosity noise on the cylinder rim)",
-        "config": {"workload": w.name, "cells": n, "primal_steps": primal, "window_steps": window,
-                   "objective": "dissipation", "adjoint": "mean-flow, tol %.0e" % args.adjoint_tol,
-                   "adjoint_iters_last": q.adj_iters},
+        "config": {"workload": w.name, "cells": n, "primal_steps": T, "window_steps": q.window,
+                   "shedding_period_steps": q.period, "objective": "dissipation",
+                   "adjoint": f"mean-flow, tol {args.adjoint_tol:g}", "adjoint_iters": q.adj_iters,
+                   "adjoint_residual": q.adj_res, "J_mean": q.J},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_primal (no window)", "bytes_per_update": bpu,
-                     "us_per_launch": avg_ms * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(khash),
+                     "kernel": "k_primal<9, double> (AA step, no window)",
+                     "bytes_per_update": bpu["primal"], "updates_per_launch": n, "us_per_launch": kus,
+                     "window_us_per_launch": prof["primal_window"]["mean_us"],
+                     "adjoint_us_per_launch": prof["adjoint"]["mean_us"],
+                     "note": "the 36 MB of FP64 populations stay resident in the 256 MB Infinity Cache"},
     }
+    if not args.no_fp32:
+        q32 = Query(w, H.FP32, T, args.adjoint_max, args.adjoint_tol, 1000, args.periods)
+        q32.run()
+        g64, g32 = q.grad, q32.grad
+        out["fp32_vs_fp64"] = {
+            "grad_rel_l2": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)),
+            "grad_cosine": float(g32 @ g64 / np.linalg.norm(g32) / np.linalg.norm(g64)),
+            "J_mean_rel": abs(q32.J - q.J) / abs(q.J),
+            "window_steps": q32.window, "adjoint_iters": q32.adj_iters,
+        }
+        log("fp32 vs fp64:", out["fp32_vs_fp64"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_primal, args.cpu_adjoint)
     print(json.dumps(out), flush=True)

@@ -220,13 +220,20 @@ hlbm_status hlbm_get_adjoint(hlbm_lattice lat, double* phi, int64_t n_values, in
 hlbm_status hlbm_get_field(hlbm_lattice lat, int32_t field, double* out, int64_t n_values,
                            int32_t mem);
 hlbm_status hlbm_synchronize(hlbm_lattice lat);
-/* Kernel-time bookkeeping by HIP events on the lattice's stream: with
- * enable != 0 each primal and adjoint sweep batch is bracketed by events.
- * hlbm_profile_get returns the summed milliseconds and kernel launch counts
- * of the primal and adjoint sweeps since the last enable. */
-hlbm_status hlbm_profile_enable(hlbm_lattice lat, int32_t enable);
-hlbm_status hlbm_profile_get(hlbm_lattice lat, double* primal_ms, int64_t* primal_launches,
-                             double* adjoint_ms, int64_t* adjoint_launches);
+/* Kernel timing by HIP events on the lattice's stream.  With every > 0, one
+ * launch in `every` of each sweep kind is bracketed by a pair of events and
+ * timed on its own (the others run untouched); every = 0 switches it off and
+ * clears the statistics.  kind: 0 primal sweep, 1 primal sweep with window
+ * accumulation, 2 adjoint sweep.  hlbm_profile_get returns the mean duration
+ * of the sampled launches in microseconds and how many were sampled. */
+hlbm_status hlbm_profile_enable(hlbm_lattice lat, int32_t every);
+hlbm_status hlbm_profile_get(hlbm_lattice lat, int32_t kind, double* mean_us, int64_t* sampled);
+/* Velocity probe: every primal step records u_y of cell (x, y, z) (the
+ * pre-collision state of that step) into a device ring of `capacity` values
+ * (capacity 0 removes the probe).  hlbm_get_probe copies the last
+ * min(steps, capacity) values, oldest first, and their count. */
+hlbm_status hlbm_set_probe(hlbm_lattice lat, int32_t x, int32_t y, int32_t z, int64_t capacity);
+hlbm_status hlbm_get_probe(hlbm_lattice lat, double* out, int64_t capacity, int64_t* count);
 /* Algorithmic bytes per lattice update of the primal sweep (accumulate = 0 or
  * 1) and of the adjoint sweep for this lattice's configuration. */
 hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* primal_window,

@@ -192,6 +192,26 @@ hlbm_status zero_window(hlbm_lattice_s* L) {
   return HLBM_OK;
 }
 
+// Launches one sweep of the given kind; one launch in prof_every is timed by
+// its own pair of events.
+template <typename F>
+hlbm_status timed_launch(hlbm_lattice_s* L, int kind, F&& launch) {
+  const bool sample = L->prof_every > 0 && (L->prof_count[kind] % L->prof_every) == 0;
+  L->prof_count[kind] += 1;
+  if (sample) HIP_TRY(hipEventRecord(L->ev0, L->stream));
+  hipError_t e = launch();
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+  if (sample) {
+    HIP_TRY(hipEventRecord(L->ev1, L->stream));
+    HIP_TRY(hipEventSynchronize(L->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
+    L->prof_ms[kind] += ms;
+    L->prof_sampled[kind] += 1;
+  }
+  return HLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -289,7 +309,7 @@ void hlbm_destroy(hlbm_lattice L) {
   (void)hipStreamSynchronize(L->stream);
   void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
-                  L->red, L->usnap};
+                  L->red, L->usnap, L->probe_buf};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
   if (L->ev0) (void)hipEventDestroy(L->ev0);
@@ -456,23 +476,68 @@ hlbm_status hlbm_window_count(hlbm_lattice L, int64_t* samples) {
   return HLBM_OK;
 }
 
-hlbm_status hlbm_profile_enable(hlbm_lattice L, int32_t enable) {
+hlbm_status hlbm_profile_enable(hlbm_lattice L, int32_t every) {
   CHECK_LAT(L);
-  L->prof = enable ? 1 : 0;
-  L->prim_ms = L->adj_ms = 0.0;
-  L->prim_launch = L->adj_launch = 0;
+  if (every < 0) return fail(HLBM_E_INVALID, "every must be >= 0");
+  L->prof_every = every;
+  for (int k = 0; k < 3; ++k) {
+    L->prof_count[k] = 0;
+    L->prof_sampled[k] = 0;
+    L->prof_ms[k] = 0.0;
+  }
   return HLBM_OK;
 }
 
-hlbm_status hlbm_profile_get(hlbm_lattice L, double* primal_ms, int64_t* primal_launches, double* adjoint_ms,
-                             int64_t* adjoint_launches) {
+hlbm_status hlbm_profile_get(hlbm_lattice L, int32_t kind, double* mean_us, int64_t* sampled) {
   CHECK_LAT(L);
-  if (primal_ms) *primal_ms = L->prim_ms;
-  if (primal_launches) *primal_launches = L->prim_launch;
-  if (adjoint_ms) *adjoint_ms = L->adj_ms;
-  if (adjoint_launches) *adjoint_launches = L->adj_launch;
+  if (kind < 0 || kind > 2) return fail(HLBM_E_INVALID, "kind must be 0, 1 or 2");
+  const int64_t n = L->prof_sampled[kind];
+  if (mean_us) *mean_us = n ? 1e3 * L->prof_ms[kind] / (double)n : 0.0;
+  if (sampled) *sampled = n;
   return HLBM_OK;
 }
+
+hlbm_status hlbm_set_probe(hlbm_lattice L, int32_t x, int32_t y, int32_t z, int64_t capacity) {
+  CHECK_LAT(L);
+  if (capacity < 0) return fail(HLBM_E_INVALID, "capacity must be >= 0");
+  if (capacity == 0) {
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    dev_free(L->probe_buf);
+    L->probe_buf = nullptr;
+    L->probe_cap = L->probe_n = 0;
+    L->probe_cell = -1;
+    return HLBM_OK;
+  }
+  if (x < 0 || x >= L->desc.nx || y < 0 || y >= L->desc.ny || z < 0 || z >= L->desc.nz)
+    return fail(HLBM_E_INVALID, "probe outside the lattice");
+  if (capacity != L->probe_cap) {
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    dev_free(L->probe_buf);
+    L->probe_buf = nullptr;
+    hlbm_status s = dev_alloc((void**)&L->probe_buf, sizeof(double) * (size_t)capacity);
+    if (s != HLBM_OK) return s;
+  }
+  L->probe_cap = capacity;
+  L->probe_n = 0;
+  L->probe_cell = (int64_t)x + (int64_t)L->desc.nx * ((int64_t)y + (int64_t)L->desc.ny * z);
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_get_probe(hlbm_lattice L, double* out, int64_t capacity, int64_t* count) {
+  CHECK_LAT(L);
+  if (!out || !count) return fail(HLBM_E_INVALID, "null output");
+  if (!L->probe_buf) return fail(HLBM_E_STATE, "no probe set");
+  const int64_t n = L->probe_n < L->probe_cap ? L->probe_n : L->probe_cap;
+  if (capacity < n) return fail(HLBM_E_INVALID, "output holds %lld values, %lld needed", (long long)capacity, (long long)n);
+  std::vector<double> ring((size_t)L->probe_cap);
+  HIP_TRY(hipMemcpyAsync(ring.data(), L->probe_buf, sizeof(double) * L->probe_cap, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  const int64_t start = (L->probe_n <= L->probe_cap) ? 0 : (L->probe_n % L->probe_cap);
+  for (int64_t i = 0; i < n; ++i) out[i] = ring[(size_t)((start + i) % L->probe_cap)];
+  *count = n;
+  return HLBM_OK;
+}
+
 
 hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate, double steady_tol,
                             int64_t check_every, int64_t* steps_done) {
@@ -503,21 +568,13 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
   while (done < n_steps) {
     int64_t chunk = n_steps - done;
     if (steady_tol > 0.0 && chunk > check_every) chunk = check_every;
-    if (L->prof) HIP_TRY(hipEventRecord(L->ev0, L->stream));
     for (int64_t k = 0; k < chunk; ++k) {
-      hipError_t e = launch_primal_step(L, accumulate);
-      if (e != hipSuccess) return fail(HLBM_E_DEVICE, "primal step: %s", hipGetErrorString(e));
+      s = timed_launch(L, accumulate ? 1 : 0, [&] { return launch_primal_step(L, accumulate); });
+      if (s != HLBM_OK) return s;
       L->parity ^= 1;
       L->steps += 1;
       if (accumulate) L->nsamp += 1;
-    }
-    if (L->prof) {
-      HIP_TRY(hipEventRecord(L->ev1, L->stream));
-      HIP_TRY(hipEventSynchronize(L->ev1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
-      L->prim_ms += ms;
-      L->prim_launch += chunk;
+      if (L->probe_buf) L->probe_n += 1;
     }
     done += chunk;
     if (steady_tol > 0.0) {
@@ -536,10 +593,6 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     }
   }
   if (steps_done) *steps_done = done;
-  if (L->prof == 0) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(HLBM_E_DEVICE, "primal: %s", hipGetErrorString(e));
-  }
   if (steady_tol > 0.0 && !converged) result = HLBM_W_NOT_CONVERGED;
   L->adj_ready = 0;
   return result;
@@ -619,20 +672,11 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
   while (done < iters) {
     int64_t chunk = iters - done;
     if (o->tol > 0.0 && chunk > M) chunk = M;
-    if (L->prof) HIP_TRY(hipEventRecord(L->ev0, L->stream));
     for (int64_t k = 0; k < chunk; ++k) {
-      hipError_t e = launch_adjoint_step(L);
-      if (e != hipSuccess) return fail(HLBM_E_DEVICE, "adjoint step: %s", hipGetErrorString(e));
+      s = timed_launch(L, 2, [&] { return launch_adjoint_step(L); });
+      if (s != HLBM_OK) return s;
       L->pvcur ^= 1;
       L->adj_iters += 1;
-    }
-    if (L->prof) {
-      HIP_TRY(hipEventRecord(L->ev1, L->stream));
-      HIP_TRY(hipEventSynchronize(L->ev1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
-      L->adj_ms += ms;
-      L->adj_launch += chunk;
     }
     done += chunk;
     if (o->tol > 0.0) {

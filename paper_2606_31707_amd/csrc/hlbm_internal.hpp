@@ -63,11 +63,17 @@ struct hlbm_lattice_s {
   double* usnap = nullptr;    // dim * plane steady-check snapshot
   int usnap_valid = 0;
 
-  // profiling
-  int prof = 0;
-  double prim_ms = 0.0, adj_ms = 0.0;
-  int64_t prim_launch = 0, adj_launch = 0;
+  // profiling: one launch in prof_every of each kind is timed by events
+  int64_t prof_every = 0;
+  int64_t prof_count[3] = {0, 0, 0};   // launches seen per kind
+  int64_t prof_sampled[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // velocity probe
+  int64_t probe_cell = -1;
+  double* probe_buf = nullptr;
+  int64_t probe_cap = 0, probe_n = 0;
 };
 
 namespace hlbm {
@@ -78,6 +84,8 @@ struct Coll {
   double kS;      // 18 sqrt(2) Cs^2
   int smag;       // closure on
   double force[3];
+  int64_t probe_cell;  // cell whose u_y is recorded (-1: none)
+  double* probe_out;   // destination of this step's probe value
 };
 
 struct ObjBox {

@@ -299,6 +299,7 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
   const T ir = (T)1 / rho;
   const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
 
+  if (cell == c.probe_cell) *c.probe_out = (double)uy;
   T omega = (T)c.omega0;
   T taue = (T)c.tau0;
   if (c.smag) {
@@ -1066,6 +1067,12 @@ Coll make_coll(const hlbm_lattice_s* L) {
   c.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
   c.smag = L->desc.smagorinsky_cs > 0.0;
   for (int a = 0; a < 3; ++a) c.force[a] = L->desc.force[a];
+  c.probe_cell = -1;
+  c.probe_out = nullptr;
+  if (L->probe_buf != nullptr && L->probe_cap > 0) {
+    c.probe_cell = L->probe_cell;
+    c.probe_out = L->probe_buf + (L->probe_n % L->probe_cap);
+  }
   return c;
 }
 

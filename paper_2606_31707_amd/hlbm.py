@@ -37,7 +37,10 @@ EXPORTS = [
     "hlbm_window_count", "hlbm_get_objective", "hlbm_solve_adjoint", "hlbm_get_gradient",
     "hlbm_get_adjoint", "hlbm_get_field", "hlbm_synchronize", "hlbm_profile_enable",
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
+    "hlbm_set_probe", "hlbm_get_probe",
 ]
+
+PROFILE_PRIMAL, PROFILE_PRIMAL_WINDOW, PROFILE_ADJOINT = 0, 1, 2
 
 
 class Desc(C.Structure):
@@ -125,7 +128,9 @@ def load_library(path: str = LIB_PATH):
         "hlbm_get_field": (i32, [vp, i32, vp, i64, i32]),
         "hlbm_synchronize": (i32, [vp]),
         "hlbm_profile_enable": (i32, [vp, i32]),
-        "hlbm_profile_get": (i32, [vp, P(dbl), P(i64), P(dbl), P(i64)]),
+        "hlbm_profile_get": (i32, [vp, i32, P(dbl), P(i64)]),
+        "hlbm_set_probe": (i32, [vp, i32, i32, i32, i64]),
+        "hlbm_get_probe": (i32, [vp, vp, i64, P(i64)]),
         "hlbm_bytes_per_update": (i32, [vp, P(dbl), P(dbl), P(dbl)]),
         "hlbm_status_string": (C.c_char_p, [i32]),
         "hlbm_last_error": (C.c_char_p, []),
@@ -315,15 +320,29 @@ class Lattice:
     def synchronize(self):
         _check(self._lib.hlbm_synchronize(self._h))
 
-    def profile_enable(self, on=True):
-        _check(self._lib.hlbm_profile_enable(self._h, int(bool(on))))
+    def profile_enable(self, every=1):
+        """Times one launch in `every` of each sweep kind with HIP events (0: off)."""
+        _check(self._lib.hlbm_profile_enable(self._h, int(every)))
 
     def profile(self):
-        pm, am = C.c_double(), C.c_double()
-        pl, al = C.c_int64(), C.c_int64()
-        _check(self._lib.hlbm_profile_get(self._h, C.byref(pm), C.byref(pl), C.byref(am), C.byref(al)))
-        return {"primal_ms": pm.value, "primal_launches": pl.value,
-                "adjoint_ms": am.value, "adjoint_launches": al.value}
+        out = {}
+        for kind, name in ((PROFILE_PRIMAL, "primal"), (PROFILE_PRIMAL_WINDOW, "primal_window"),
+                           (PROFILE_ADJOINT, "adjoint")):
+            us, n = C.c_double(), C.c_int64()
+            _check(self._lib.hlbm_profile_get(self._h, kind, C.byref(us), C.byref(n)))
+            out[name] = {"mean_us": us.value, "sampled": n.value}
+        return out
+
+    def set_probe(self, x, y, z=0, capacity=1 << 18):
+        _check(self._lib.hlbm_set_probe(self._h, int(x), int(y), int(z), int(capacity)))
+        self._probe_cap = int(capacity)
+
+    def probe(self) -> np.ndarray:
+        cap = getattr(self, "_probe_cap", 0)
+        out = np.empty(max(cap, 1), dtype=np.float64)
+        cnt = C.c_int64()
+        _check(self._lib.hlbm_get_probe(self._h, out.ctypes.data_as(C.c_void_p), cap, C.byref(cnt)))
+        return out[: cnt.value].copy()
 
     def bytes_per_update(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()

@@ -213,3 +213,19 @@ def test_errors_are_reported():
     assert e.value.status == H.E_INVALID
     with pytest.raises(H.HlbmError):
         G2.set_objective(H.OBJ_FFA, (0, 0, 0), (0, 9, 0))  # inlet column
+
+
+def test_velocity_probe_records_each_step():
+    s = channel(tau=0.56, u_in=0.05)
+    say("probe")
+    L, G = make_oracle(s), make_gpu(s)
+    px, py = 60, 25
+    G.set_probe(px, py, 0, capacity=50)
+    ref = []
+    for _ in range(80):  # ring of 50: keeps the last 50 steps
+        ref.append(L.moments()[1][1][px + s.nx * py])
+        L.step(1)
+    G.run_primal(80)
+    got = G.probe()
+    assert len(got) == 50
+    assert np.abs(got - np.array(ref[-50:])).max() < 1e-12 * np.abs(ref).max()
