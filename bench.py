@@ -31,7 +31,8 @@ from paper_2606_31707_amd import hlbm as H  # noqa: E402
 from paper_2606_31707_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2606_31707_amd", "csrc", "hlbm_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_31707_amd", "csrc", f)
+                  for f in ("hlbm_device.hpp", "hlbm_kernels.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_primal_d2q9_fp64_vortex_re100_traffic.json")
 
 
@@ -122,6 +123,14 @@ def cpu_baseline(w: I.Workload, primal_steps: int, adj_iters: int):
                       f"preparation, {adj_iters} adjoint iterations and the gradient ({dt:.1f} s of CPU)"}
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the device code (the counters are tied to it)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel_hash: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source."""
@@ -143,12 +152,25 @@ def main():
     ap.add_argument("--periods", type=int, default=10)
     ap.add_argument("--adjoint-max", type=int, default=60000)
     ap.add_argument("--adjoint-tol", type=float, default=1e-6)
-    ap.add_argument("--profile-every", type=int, default=50)
+    ap.add_argument("--profile-every", type=int, default=49)  # odd: samples both AA parities
     ap.add_argument("--cpu-primal", type=int, default=40)
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration_mib:
+        import torch
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,8 +203,8 @@ def main():
     bpu = q.G.bytes_per_update()
     n = w.n
     kus = prof["primal"]["mean_us"]
-    achieved = bpu["primal"] * n / (kus * 1e-6) / 1e9
-    khash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    achieved = bpu["primal"] * n / (kus * 1e-6) / 1e9 if kus > 0 else 0.0
+    khash = kernel_source_hash()
     log(f"k_primal: {kus:.2f} us/launch ({prof['primal']['sampled']} sampled), {achieved:.0f} GB/s; "
         f"window {prof['primal_window']['mean_us']:.2f} us; adjoint {prof['adjoint']['mean_us']:.2f} us")
 

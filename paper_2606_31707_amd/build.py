@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libhlbm.so")
-SOURCES = ["hlbm_kernels.hip", "hlbm_api.hip"]
+SOURCES = ["hlbm_launch.hip", "hlbm_api.hip"]
 ARCH = os.environ.get("HLBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -193,16 +193,14 @@ hlbm_status zero_window(hlbm_lattice_s* L) {
 }
 
 // Launches one sweep of the given kind; one launch in prof_every is timed by
-// its own pair of events.
+// events the runtime records at that kernel's own start and end.
 template <typename F>
 hlbm_status timed_launch(hlbm_lattice_s* L, int kind, F&& launch) {
   const bool sample = L->prof_every > 0 && (L->prof_count[kind] % L->prof_every) == 0;
   L->prof_count[kind] += 1;
-  if (sample) HIP_TRY(hipEventRecord(L->ev0, L->stream));
-  hipError_t e = launch();
+  hipError_t e = sample ? launch(L->ev0, L->ev1) : launch(nullptr, nullptr);
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
   if (sample) {
-    HIP_TRY(hipEventRecord(L->ev1, L->stream));
     HIP_TRY(hipEventSynchronize(L->ev1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
@@ -211,7 +209,6 @@ hlbm_status timed_launch(hlbm_lattice_s* L, int kind, F&& launch) {
   }
   return HLBM_OK;
 }
-
 }  // namespace
 
 extern "C" {
@@ -569,7 +566,8 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     int64_t chunk = n_steps - done;
     if (steady_tol > 0.0 && chunk > check_every) chunk = check_every;
     for (int64_t k = 0; k < chunk; ++k) {
-      s = timed_launch(L, accumulate ? 1 : 0, [&] { return launch_primal_step(L, accumulate); });
+      s = timed_launch(L, accumulate ? 1 : 0,
+                       [&](hipEvent_t a, hipEvent_t b) { return launch_primal_step(L, accumulate, a, b); });
       if (s != HLBM_OK) return s;
       L->parity ^= 1;
       L->steps += 1;
@@ -673,7 +671,7 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
     int64_t chunk = iters - done;
     if (o->tol > 0.0 && chunk > M) chunk = M;
     for (int64_t k = 0; k < chunk; ++k) {
-      s = timed_launch(L, 2, [&] { return launch_adjoint_step(L); });
+      s = timed_launch(L, 2, [&](hipEvent_t a, hipEvent_t b) { return launch_adjoint_step(L, a, b); });
       if (s != HLBM_OK) return s;
       L->pvcur ^= 1;
       L->adj_iters += 1;

@@ -1,0 +1,318 @@
+// hlbm_launch.hip -- host-side launchers of the gfx950 kernels: grid shape,
+// template dispatch over stencil and precision, optional start/stop events
+// recorded at the kernel's own start and end (hipExtLaunchKernelGGL).
+#include <hip/hip_ext.h>
+
+#include "hlbm_kernels.hpp"
+
+namespace hlbm {
+
+// Launches `kernel`; with events, the runtime records e0/e1 when the kernel
+// itself starts and ends (no dispatch latency in the measurement).
+template <typename K, typename... Args>
+static void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t e0, hipEvent_t e1,
+                     Args... args) {
+  if (e0 != nullptr)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+}
+
+Geo make_geo(const hlbm_lattice_s* L) {
+  Geo g;
+  g.nx = L->desc.nx;
+  g.ny = L->desc.ny;
+  g.nz = L->desc.nz;
+  g.bcx = L->desc.bc_x;
+  g.bcy = L->desc.bc_y;
+  g.bcz = L->desc.stencil == HLBM_D2Q9 ? BC_PERIODIC : L->desc.bc_z;
+  g.plane = L->plane;
+  g.gplane = L->gplane;
+  g.inlet_profile = L->desc.inlet_profile;
+  g.u_in = L->desc.u_in;
+  return g;
+}
+
+ObjBox make_obj(const hlbm_lattice_s* L) {
+  ObjBox o;
+  o.active = L->obj_set;
+  o.kind = L->obj_kind;
+  for (int a = 0; a < 3; ++a) {
+    o.lo[a] = L->lo[a];
+    o.rn[a] = L->rn[a];
+  }
+  o.rplane = L->rplane;
+  o.u0 = L->u0;
+  o.p0 = L->p0;
+  o.tau0 = L->desc.tau;
+  return o;
+}
+
+Coll make_coll(const hlbm_lattice_s* L) {
+  Coll c;
+  c.tau0 = L->desc.tau;
+  c.omega0 = 1.0 / L->desc.tau;
+  c.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
+  c.smag = L->desc.smagorinsky_cs > 0.0;
+  for (int a = 0; a < 3; ++a) c.force[a] = L->desc.force[a];
+  c.probe_cell = -1;
+  c.probe_out = nullptr;
+  if (L->probe_buf != nullptr && L->probe_cap > 0) {
+    c.probe_cell = L->probe_cell;
+    c.probe_out = L->probe_buf + (L->probe_n % L->probe_cap);
+  }
+  return c;
+}
+
+dim3 cell_grid(const hlbm_lattice_s* L) {
+  return dim3((L->desc.nx + BX - 1) / BX, (L->desc.ny + BY - 1) / BY, L->desc.nz);
+}
+
+static const dim3 kBlock(BX, BY, 1);
+
+template <int Q, typename S>
+static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+  using Dd = typename Prec<S>::Dd;
+  const Geo g = make_geo(L);
+  const Coll c = make_coll(L);
+  const ObjBox ob = make_obj(L);
+  Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
+          c.smag ? L->acc_tau : nullptr, L->acc_obj};
+  S* A = (S*)L->f;
+  const Dd* dp = (const Dd*)L->dpor;
+  S* gh = (S*)L->ghost;
+  const dim3 grid = cell_grid(L);
+  if (L->parity == 0) {
+    if (accumulate)
+      launch_k(k_primal<Q, S, false, true>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    else
+      launch_k(k_primal<Q, S, false, false>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+  } else {
+    if (accumulate)
+      launch_k(k_primal<Q, S, true, true>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    else
+      launch_k(k_primal<Q, S, true, false>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+  }
+  return hipGetLastError();
+}
+
+#define HLBM_DISPATCH(L, FN, ...)                                             \
+  do {                                                                        \
+    const int key_ = (L)->desc.stencil * 3 + (L)->desc.precision;            \
+    switch (key_) {                                                           \
+      case 0: return FN<9, double>(__VA_ARGS__);                              \
+      case 1: return FN<9, float>(__VA_ARGS__);                               \
+      case 2: return FN<9, _Float16>(__VA_ARGS__);                            \
+      case 3: return FN<19, double>(__VA_ARGS__);                             \
+      case 4: return FN<19, float>(__VA_ARGS__);                              \
+      case 5: return FN<19, _Float16>(__VA_ARGS__);                           \
+      default: return hipErrorInvalidValue;                                   \
+    }                                                                         \
+  } while (0)
+
+hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+  HLBM_DISPATCH(L, primal_impl, L, accumulate, e0, e1);
+}
+
+template <int Q, typename S>
+static hipError_t init_impl(hlbm_lattice_s* L, double rho0, const double* u_dev) {
+  k_init<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (S*)L->f,
+                                                       (const typename Prec<S>::Dd*)L->dpor, rho0,
+                                                       u_dev, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev) {
+  HLBM_DISPATCH(L, init_impl, L, rho0, u_dev);
+}
+
+hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
+                           const double* noise_dev, int mode, double box_half) {
+  if (L->desc.precision == HLBM_FP64)
+    k_cylinder<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, xc, yc,
+                                                               D, noise_dev, mode, box_half);
+  else
+    k_cylinder<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, xc, yc, D,
+                                                              noise_dev, mode, box_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev) {
+  if (L->desc.precision == HLBM_FP64)
+    k_set_porosity<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, d_dev,
+                                                                   bad_dev);
+  else
+    k_set_porosity<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, d_dev,
+                                                                  bad_dev);
+  return hipGetLastError();
+}
+
+template <int Q, typename S>
+static hipError_t gather_impl(hlbm_lattice_s* L, double* out) {
+  k_gather<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f,
+                                                         (const S*)L->ghost, L->parity, out, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev) { HLBM_DISPATCH(L, gather_impl, L, out_dev); }
+
+template <int Q, typename S>
+static hipError_t scatter_impl(hlbm_lattice_s* L, const double* in) {
+  k_scatter<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (S*)L->f, in, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_scatter(hlbm_lattice_s* L, const double* in_dev) {
+  HLBM_DISPATCH(L, scatter_impl, L, in_dev);
+}
+
+template <int Q, typename S>
+static hipError_t moments_impl(hlbm_lattice_s* L, double* rho, double* u) {
+  k_moments<Q, S><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f,
+                                                          (const S*)L->ghost, L->parity, rho, u, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_moments(hlbm_lattice_s* L, double* rho_dev, double* u_dev) {
+  HLBM_DISPATCH(L, moments_impl, L, rho_dev, u_dev);
+}
+
+hipError_t launch_mean_fields(hlbm_lattice_s* L, int field, double* out_dev) {
+  const double inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  if (L->desc.stencil == HLBM_D2Q9)
+    k_mean_fields<9><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), field, L->acc_rho, L->acc_j,
+                                                             L->acc_tau, inv, out_dev, L->n);
+  else
+    k_mean_fields<19><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), field, L->acc_rho, L->acc_j,
+                                                              L->acc_tau, inv, out_dev, L->n);
+  return hipGetLastError();
+}
+
+static int grid_blocks(const dim3& g) { return (int)(g.x * g.y * g.z); }
+
+template <int Q, typename S>
+static hipError_t steady_impl(hlbm_lattice_s* L, int first, double* partials, int* nb) {
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  k_steady_check<Q, S><<<grid, kBlock, 0, L->stream>>>(make_geo(L), (const S*)L->f, (const S*)L->ghost,
+                                                       L->parity, L->usnap, first, partials);
+  return hipGetLastError();
+}
+hipError_t launch_steady_check(hlbm_lattice_s* L, int first, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, steady_impl, L, first, partials, nblocks);
+}
+
+template <int Q, typename S>
+static hipError_t objective_impl(hlbm_lattice_s* L, int which, double* partials, int* nb) {
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  const double inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  k_objective<Q, S><<<grid, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+                                                    (const S*)L->ghost, L->parity,
+                                                    (const typename Prec<S>::Dd*)L->dpor, which,
+                                                    L->acc_obj, inv, partials);
+  return hipGetLastError();
+}
+hipError_t launch_objective(hlbm_lattice_s* L, int which, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, objective_impl, L, which, partials, nblocks);
+}
+
+hipError_t launch_finalize_sum(hlbm_lattice_s* L, const double* partials, int n, double* out) {
+  k_finalize_sum<<<1, 256, 0, L->stream>>>(partials, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_max2(hlbm_lattice_s* L, const double* partials, int n, double* out) {
+  k_finalize_max2<<<1, 256, 0, L->stream>>>(partials, n, out);
+  return hipGetLastError();
+}
+
+// adjoint storage type: FP64 form -> double, FP32/FP16S forms -> float
+template <typename S>
+struct AdjT {
+  using type = float;
+};
+template <>
+struct AdjT<double> {
+  using type = double;
+};
+
+template <int Q, typename S>
+static hipError_t prep_impl(hlbm_lattice_s* L, int source, double tau_adj, int turb) {
+  using SA = typename AdjT<S>::type;
+  PrepIn pin;
+  pin.acc_rho = L->acc_rho;
+  pin.acc_j = L->acc_j;
+  pin.acc_f = L->acc_f;
+  pin.acc_tau = L->acc_tau;
+  pin.acc_obj = L->acc_obj;
+  pin.inv = L->nsamp ? 1.0 / (double)L->nsamp : 0.0;
+  pin.source = source;
+  pin.smag = L->desc.smagorinsky_cs > 0.0;
+  pin.turb = turb;
+  pin.tau0 = L->desc.tau;
+  pin.tau_adj = tau_adj;
+  pin.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
+  k_adjoint_prep<Q, S, SA><<<cell_grid(L), kBlock, 0, L->stream>>>(
+      make_geo(L), make_obj(L), pin, (const S*)L->f, (const S*)L->ghost, L->parity,
+      (const typename Prec<S>::Dd*)L->dpor, (SA*)L->prep, L->src, L->gdat, L->oprep);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_prep(hlbm_lattice_s* L, int source, double tau_adj, int turb) {
+  HLBM_DISPATCH(L, prep_impl, L, source, tau_adj, turb);
+}
+
+template <int Q, typename S>
+static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
+  using SA = typename AdjT<S>::type;
+  AdjC ac;
+  ac.les = L->adj_les;
+  ac.diff = L->adj_diff;
+  ac.omega0 = L->adj_omega;  // used when the relaxation time is uniform (no closure)
+  const Geo g = make_geo(L);
+  const ObjBox ob = make_obj(L);
+  SA* A = (SA*)L->phi;
+  const SA* pin = (const SA*)L->pv[L->pvcur];
+  SA* pout = (SA*)L->pv[L->pvcur ^ 1];
+  const SA* prep = (const SA*)L->prep;
+  if ((L->adj_iters & 1) == 0)
+    launch_k(k_adjoint<Q, SA, false>, cell_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
+             L->oprep, pin, pout);
+  else
+    launch_k(k_adjoint<Q, SA, true>, cell_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
+             L->oprep, pin, pout);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_step(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
+  HLBM_DISPATCH(L, adjoint_impl, L, e0, e1);
+}
+
+template <int Q, typename S>
+static hipError_t residual_impl(hlbm_lattice_s* L, int first, double* partials, int* nb) {
+  using SA = typename AdjT<S>::type;
+  const dim3 grid = cell_grid(L);
+  *nb = grid_blocks(grid);
+  k_adjoint_residual<Q, SA><<<grid, kBlock, 0, L->stream>>>(make_geo(L), (const SA*)L->phi, (SA*)L->snap,
+                                                            first, partials);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partials, int* nblocks) {
+  HLBM_DISPATCH(L, residual_impl, L, first, partials, nblocks);
+}
+
+template <int Q, typename S>
+static hipError_t gradient_impl(hlbm_lattice_s* L, double* g_dev) {
+  using SA = typename AdjT<S>::type;
+  k_gradient<Q, SA, typename Prec<S>::Dd><<<cell_grid(L), kBlock, 0, L->stream>>>(
+      make_geo(L), make_obj(L), (const SA*)L->phi, (const typename Prec<S>::Dd*)L->dpor, L->gdat, L->src,
+      g_dev);
+  return hipGetLastError();
+}
+hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev) { HLBM_DISPATCH(L, gradient_impl, L, g_dev); }
+
+template <int Q, typename S>
+static hipError_t adjoint_gather_impl(hlbm_lattice_s* L, double* out) {
+  using SA = typename AdjT<S>::type;
+  k_adjoint_gather<Q, SA><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (const SA*)L->phi, out, L->n);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev) {
+  HLBM_DISPATCH(L, adjoint_gather_impl, L, out_dev);
+}
+
+}  // namespace hlbm
