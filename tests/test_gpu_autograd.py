@@ -1,0 +1,128 @@
+"""torch.autograd.Function over the HLBM objective (the differentiation batch:
+seeded porosity fields on the 400 x 160 Re = 40 channel, drag objective).
+
+- parity: autograd gradient (FP64) vs the oracle gradient at the same primal
+  step count and adjoint iteration count (FFA source, well conditioned);
+- FP32 form vs the FP64 oracle (stated error);
+- finite differences of the converged steady J along seeded unit directions
+  (eps = 1e-4, FP64 GPU re-solves) vs the autograd gradient;
+- gJ scaling through a batch loss.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_31707_amd import inputs as I
+from tests.pairs import Spec, make_oracle, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def field_spec(seed=400, scale=1.0):
+    w = I.autograd_re40(seed)
+    if scale != 1.0:
+        w = I.scaled(w, scale)
+    s = Spec(nx=w.nx, ny=w.ny, tau=w.tau, u_in=w.u_max, cyl=(w.xc, w.yc, w.D), noise_mode=w.noise_mode,
+             noise=I.porosity_noise(w), box_half=w.box_half, obj=(O.OBJ_FFA, w.lo, w.hi, w.u0))
+    return w, s
+
+
+def lattice_for(w, precision):
+    from paper_2606_31707_amd import autograd as A
+    from paper_2606_31707_amd import hlbm as H
+    G = A.make_lattice(precision=precision, nx=w.nx, ny=w.ny, tau=w.tau, u_in=w.u_max,
+                       bc_x=H.BC_INLET_OUTLET, bc_y=H.BC_WALLS, inlet_profile=H.INLET_PARABOLIC)
+    G.set_objective(H.OBJ_FFA, w.lo, w.hi, u0=w.u0)
+    return G
+
+
+def porosity_of(s):
+    L = make_oracle(s)
+    return L.porosity()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_reference(seed, steps, iters):
+    w, s = field_spec(seed)
+    L = make_oracle(s)
+    L.step(steps)
+    L.adjoint_prepare(0)
+    L.adjoint_iterate(iters)
+    return L.porosity(), L.gradient(), L.objective()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-3)])
+def test_autograd_gradient_vs_oracle(precision, tol):
+    import torch
+    from paper_2606_31707_amd import autograd as A
+    w, s = field_spec(400)
+    say("autograd vs oracle", precision)
+    d_ref, g_ref, J_ref = oracle_reference(400, 1200, 400)
+    G = lattice_for(w, precision)
+    d = torch.tensor(d_ref, device="cuda", requires_grad=True)
+    plan = A.Plan(primal_steps=1200, adjoint_iters=400)
+    J = A.objective(d, G, plan)
+    J.backward()
+    g = d.grad.cpu().numpy()
+    e = rel_err(g, g_ref)
+    cos = float(g @ g_ref / np.linalg.norm(g) / np.linalg.norm(g_ref))
+    print(f"form {precision}: gradient rel err {e:.3e}, cosine {cos:.12f}, J {J.item():.9e} vs {J_ref:.9e}",
+          flush=True)
+    assert e < tol
+    assert abs(J.item() - J_ref) < max(tol, 1e-10) * 10 * abs(J_ref)
+
+
+def test_autograd_finite_differences_converged():
+    """Converged steady J(d) on the full 400 x 160 field; FD along seeded unit
+    directions vs the adjoint gradient."""
+    import torch
+    from paper_2606_31707_amd import autograd as A
+    w, s = field_spec(401)
+    say("autograd FD")
+    d0 = torch.tensor(porosity_of(s), device="cuda")
+    G = lattice_for(w, 0)
+    plan = A.Plan(primal_steps=400000, steady_tol=1e-13, check_every=500, adjoint_iters=400000,
+                  adjoint_tol=1e-13)
+    d = d0.clone().requires_grad_(True)
+    J = A.objective(d, G, plan)
+    J.backward()
+    g = d.grad.clone()
+    eps = 1e-4
+    errs = []
+    dn = d0.cpu().numpy()
+    inside = (dn > 1e-3) & (dn < 1 - 1e-3)  # perturbations stay within [0, 1]
+    for seed in (500, 501):
+        rng = np.random.default_rng(seed)
+        v = rng.standard_normal(w.n) * inside
+        v /= np.linalg.norm(v)
+        vt = torch.tensor(v, device="cuda")
+        Jp = A.objective(d0 + eps * vt, G, plan).item()
+        Jm = A.objective(d0 - eps * vt, G, plan).item()
+        fd = (Jp - Jm) / (2 * eps)
+        ad = float((g * vt).sum())
+        errs.append(abs(ad - fd) / abs(fd))
+        print(f"direction {seed}: adjoint {ad:.9e}, FD {fd:.9e}, rel {errs[-1]:.2e}", flush=True)
+    assert max(errs) < 1e-5
+
+
+def test_batch_loss_scales_gradients():
+    import torch
+    from paper_2606_31707_amd import autograd as A
+    say("autograd batch")
+    fields, lats = [], []
+    for seed in (402, 403):
+        w, s = field_spec(seed, scale=0.5)
+        fields.append(porosity_of(s))
+        lats.append(lattice_for(w, 0))
+    d = torch.tensor(np.stack(fields), device="cuda", requires_grad=True)
+    plan = A.Plan(primal_steps=600, adjoint_iters=200)
+    Jb = A.objective_batch(d, lats, plan)
+    (2.0 * Jb[0] - 3.0 * Jb[1]).backward()
+    g = d.grad.clone()
+    d2 = torch.tensor(np.stack(fields), device="cuda", requires_grad=True)
+    Jb2 = A.objective_batch(d2, lats, plan)
+    Jb2.sum().backward()
+    assert torch.allclose(g[0], 2.0 * d2.grad[0], rtol=1e-13, atol=0)
+    assert torch.allclose(g[1], -3.0 * d2.grad[1], rtol=1e-13, atol=0)
