@@ -143,6 +143,69 @@ def traffic_for(kernel_hash: str):
     return rec.get("bytes_per_launch")
 
 
+def report_differentiation(n_fields: int, fd_fields: int, fd_dirs: int):
+    """The differentiation batch: seeded porosity fields on the 400 x 160
+    Re = 40 channel (drag), gradients through the torch.autograd.Function in
+    FP64 and FP32 at converged steady states, and central differences of the
+    converged FP64 objective along seeded unit directions (eps = 1e-4)."""
+    import torch
+    from paper_2606_31707_amd import autograd as A
+    p64 = A.Plan(primal_steps=400000, steady_tol=1e-13, check_every=500, adjoint_iters=400000,
+                 adjoint_tol=1e-13)
+    p32 = A.Plan(primal_steps=400000, steady_tol=1e-6, check_every=500, adjoint_iters=400000,
+                 adjoint_tol=1e-6)
+    rows, fd = [], []
+    lat = {}
+    for k in range(n_fields):
+        seed = 400 + k
+        w = I.autograd_re40(seed)
+        for prec in (H.FP64, H.FP32):
+            if prec not in lat:
+                lat[prec] = A.make_lattice(precision=prec, nx=w.nx, ny=w.ny, tau=w.tau, u_in=w.u_max)
+                lat[prec].set_objective(H.OBJ_FFA, w.lo, w.hi, u0=w.u0)
+        G = lat[H.FP64]
+        G.build_cylinder(w.xc, w.yc, w.D, noise=I.porosity_noise(w), noise_mode=w.noise_mode,
+                         box_half=w.box_half)
+        d0 = torch.tensor(G.porosity(), device="cuda")
+        grads, Js, secs = {}, {}, {}
+        for prec, plan in ((H.FP64, p64), (H.FP32, p32)):
+            d = d0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            J = A.objective(d, lat[prec], plan)
+            J.backward()
+            torch.cuda.synchronize()
+            secs[prec] = time.perf_counter() - t
+            grads[prec], Js[prec] = d.grad.detach().cpu().numpy(), J.item()
+        g64, g32 = grads[H.FP64], grads[H.FP32]
+        rows.append({"seed": seed, "J_fp64": Js[H.FP64], "J_fp32_rel": abs(Js[H.FP32] - Js[H.FP64]) / abs(Js[H.FP64]),
+                     "grad_fp32_rel_l2": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)),
+                     "grad_fp32_cosine": float(g32 @ g64 / np.linalg.norm(g32) / np.linalg.norm(g64)),
+                     "seconds_fp64": secs[H.FP64], "seconds_fp32": secs[H.FP32]})
+        log(rows[-1])
+        if k < fd_fields:
+            dn = d0.cpu().numpy()
+            inside = (dn > 1e-3) & (dn < 1 - 1e-3)
+            for ds in range(500, 500 + fd_dirs):
+                v = np.random.default_rng(ds).standard_normal(w.n) * inside
+                v /= np.linalg.norm(v)
+                vt = torch.tensor(v, device="cuda")
+                Jp = A.objective(d0 + 1e-4 * vt, G, p64).item()
+                Jm = A.objective(d0 - 1e-4 * vt, G, p64).item()
+                fdv = (Jp - Jm) / 2e-4
+                ad = float(g64 @ v)
+                fd.append({"seed": seed, "direction_seed": ds, "adjoint": ad, "fd": fdv,
+                           "rel_err": abs(ad - fdv) / abs(fdv)})
+                log(fd[-1])
+    rel = [r["grad_fp32_rel_l2"] for r in rows]
+    out = {"report": "differentiation batch (400x160, Re 40, drag)", "fields": len(rows),
+           "fd_checks": len(fd), "fd_max_rel_err": max(f["rel_err"] for f in fd) if fd else None,
+           "fp32_grad_rel_l2_median": float(np.median(rel)), "fp32_grad_rel_l2_max": float(np.max(rel)),
+           "fp32_grad_cosine_min": float(min(r["grad_fp32_cosine"] for r in rows)),
+           "rows": rows, "fd": fd}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,9 +220,18 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--report", choices=["differentiation"], default=None,
+                    help="print a secondary measurement report instead of the benchmark line")
+    ap.add_argument("--fields", type=int, default=32)
+    ap.add_argument("--fd-fields", type=int, default=2)
+    ap.add_argument("--fd-directions", type=int, default=8)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.report == "differentiation":
+        report_differentiation(args.fields, args.fd_fields, args.fd_directions)
+        return
 
     if args.copy_calibration_mib:
         import torch

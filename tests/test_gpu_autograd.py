@@ -53,8 +53,12 @@ def oracle_reference(seed, steps, iters):
     return L.porosity(), L.gradient(), L.objective()
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-3)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-4)])
 def test_autograd_gradient_vs_oracle(precision, tol):
+    """Independent primal runs on both sides (1200 steps) and 400 adjoint
+    iterations: the FP64 bound is on the L2-relative error (1e-12) with a
+    max-norm guard of 5e-12 (rounding of two independent runs compounds over
+    1600 sweeps); FP32 is the stated error of that form."""
     import torch
     from paper_2606_31707_amd import autograd as A
     w, s = field_spec(400)
@@ -67,11 +71,12 @@ def test_autograd_gradient_vs_oracle(precision, tol):
     J.backward()
     g = d.grad.cpu().numpy()
     e = rel_err(g, g_ref)
+    e2 = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     cos = float(g @ g_ref / np.linalg.norm(g) / np.linalg.norm(g_ref))
-    print(f"form {precision}: gradient rel err {e:.3e}, cosine {cos:.12f}, J {J.item():.9e} vs {J_ref:.9e}",
-          flush=True)
-    assert e < tol
-    assert abs(J.item() - J_ref) < max(tol, 1e-10) * 10 * abs(J_ref)
+    print(f"form {precision}: gradient max-rel {e:.3e}, L2-rel {e2:.3e}, cosine {cos:.12f}, "
+          f"J {J.item():.9e} vs {J_ref:.9e}", flush=True)
+    assert e2 < tol and e < 5 * tol
+    assert abs(J.item() - J_ref) < 10 * tol * abs(J_ref)
 
 
 def test_autograd_finite_differences_converged():
