@@ -206,6 +206,25 @@ def report_differentiation(n_fields: int, fd_fields: int, fd_dirs: int):
     print(json.dumps(out), flush=True)
 
 
+def report_serving(n: int, rate: float, cap_gib: float, tick: int, slots: int):
+    """Continuous-batching serving of a Poisson stream of gradient queries
+    (mixed D2Q9 / D3Q19 sizes, FP32): p50/p99 latency and aggregate MLUPS."""
+    from paper_2606_31707_amd import serving as S
+    qs = S.poisson_mix(n, rate)
+    t0 = time.perf_counter()
+
+    def done(a):
+        log(f"[{time.perf_counter() - t0:7.2f} s] query {a.q.qid} ({a.q.nx}x{a.q.ny}x{a.q.nz}, Re {a.q.Re:.0f}) "
+            f"latency {a.t_done - a.q.arrival:.2f} s")
+
+    srv = S.Server(S.GPUBackend(), mem_cap_bytes=int(cap_gib * (1 << 30)), max_slots=slots, tick=tick,
+                   on_done=done)
+    st = srv.run(qs)
+    out = {"report": "serving", "queries": n, "rate_qps": rate, "mem_cap_GiB": cap_gib, "tick": tick,
+           "max_slots": slots, "precision": "fp32", **st.summary()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,17 +239,25 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--report", choices=["differentiation"], default=None,
+    ap.add_argument("--report", choices=["differentiation", "serving"], default=None,
                     help="print a secondary measurement report instead of the benchmark line")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--fd-fields", type=int, default=2)
     ap.add_argument("--fd-directions", type=int, default=8)
+    ap.add_argument("--queries", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=2.0)
+    ap.add_argument("--mem-cap-gib", type=float, default=16.0)
+    ap.add_argument("--tick", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.report == "differentiation":
         report_differentiation(args.fields, args.fd_fields, args.fd_directions)
+        return
+    if args.report == "serving":
+        report_serving(args.queries, args.rate, args.mem_cap_gib, args.tick, args.slots)
         return
 
     if args.copy_calibration_mib:

@@ -238,6 +238,38 @@ hlbm_status hlbm_get_probe(hlbm_lattice lat, double* out, int64_t capacity, int6
  * 1) and of the adjoint sweep for this lattice's configuration. */
 hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* primal_window,
                                   double* adjoint);
+/* Changes the relaxation time, Smagorinsky constant and inflow speed of an
+ * existing lattice (same validity rules as hlbm_create); the state, window
+ * and adjoint are kept but the adjoint must be prepared again.  Lets a caller
+ * reuse a resident lattice of the same shape for a new query. */
+hlbm_status hlbm_reconfigure(hlbm_lattice lat, double tau, double smagorinsky_cs, double u_in);
+
+/* ---- groups: many small lattices in one packed launch per step --------- */
+
+/* A group steps several lattices of one stencil and precision with a single
+ * kernel launch per step (and per phase kind), each member running exactly
+ * the per-cell code of its own sweep, so a member's results do not depend on
+ * the other members.  Used by the request scheduler to fill the GPU with
+ * small lattices; every launch goes to the group's stream. */
+typedef struct hlbm_group_s* hlbm_group;
+typedef enum {
+  HLBM_GROUP_PRIMAL = 0,         /* primal step */
+  HLBM_GROUP_PRIMAL_WINDOW = 1,  /* primal step with window accumulation */
+  HLBM_GROUP_ADJOINT = 2         /* adjoint iteration (adjoint already prepared) */
+} hlbm_group_mode;
+
+hlbm_status hlbm_group_create(void* stream, hlbm_group* out);
+void hlbm_group_destroy(hlbm_group g);
+/* Sets the members (the lattices stay owned by the caller) and what each does
+ * per step.  Synchronises every member's own stream.  Members must share
+ * stencil and precision; ADJOINT members need a prepared adjoint
+ * (hlbm_solve_adjoint with max_iters = 0).  Until the next hlbm_group_set the
+ * members may not be advanced by any other call.  count = 0 empties it. */
+hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, const int32_t* modes, int32_t count);
+/* Advances every member by n steps / iterations (asynchronous). */
+hlbm_status hlbm_group_step(hlbm_group g, int64_t n);
+hlbm_status hlbm_group_synchronize(hlbm_group g);
+
 const char* hlbm_status_string(hlbm_status s);
 const char* hlbm_last_error(void);
 

@@ -693,7 +693,7 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
       }
     }
   }
-  HIP_TRY(hipStreamSynchronize(L->stream));
+  if (o->tol > 0.0) HIP_TRY(hipStreamSynchronize(L->stream));
   if (rep) {
     rep->iters = done;
     rep->residual = res;
@@ -802,5 +802,158 @@ extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, dou
   if (primal) *primal = p;
   if (primal_window) *primal_window = pw;
   if (adjoint) *adjoint = a;
+  return HLBM_OK;
+}
+
+extern "C" hlbm_status hlbm_reconfigure(hlbm_lattice L, double tau, double cs, double u_in) {
+  CHECK_LAT(L);
+  hlbm_desc d = L->desc;
+  d.tau = tau;
+  d.smagorinsky_cs = cs;
+  d.u_in = u_in;
+  hlbm_status s = validate_desc(&d);
+  if (s != HLBM_OK) return s;
+  if (cs > 0.0 && L->desc.smagorinsky_cs == 0.0 && L->acc_rho && !L->acc_tau) {
+    if ((s = dev_alloc((void**)&L->acc_tau, sizeof(double) * L->plane)) != HLBM_OK) return s;
+    HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * L->plane, L->stream));
+  }
+  L->desc.tau = tau;
+  L->desc.smagorinsky_cs = cs;
+  L->desc.u_in = u_in;
+  L->adj_ready = 0;
+  return HLBM_OK;
+}
+
+extern "C" hlbm_status hlbm_group_create(void* stream, hlbm_group* out) {
+  if (!out) return fail(HLBM_E_INVALID, "null output");
+  hlbm_group_s* g = new hlbm_group_s();
+  g->stream = (hipStream_t)stream;
+  *out = g;
+  return HLBM_OK;
+}
+
+extern "C" void hlbm_group_destroy(hlbm_group g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  dev_free(g->tab_primal);
+  dev_free(g->tab_adjoint);
+  dev_free(g->first_primal);
+  dev_free(g->first_adjoint);
+  delete[] g->members;
+  delete[] g->modes;
+  delete g;
+}
+
+extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, const int32_t* modes, int32_t count) {
+  if (!g) return fail(HLBM_E_INVALID, "null group");
+  if (count < 0 || (count > 0 && (!lats || !modes))) return fail(HLBM_E_INVALID, "bad member list");
+  for (int i = 0; i < count; ++i) {
+    hlbm_lattice_s* L = lats[i];
+    if (!L) return fail(HLBM_E_INVALID, "null member %d", i);
+    if (modes[i] < HLBM_GROUP_PRIMAL || modes[i] > HLBM_GROUP_ADJOINT) return fail(HLBM_E_INVALID, "bad mode");
+    if (L->desc.stencil != lats[0]->desc.stencil || L->desc.precision != lats[0]->desc.precision)
+      return fail(HLBM_E_INVALID, "members must share stencil and precision");
+    if (modes[i] == HLBM_GROUP_ADJOINT && !L->adj_ready)
+      return fail(HLBM_E_STATE, "member %d: adjoint not prepared", i);
+    for (int j = 0; j < i; ++j)
+      if (lats[j] == L) return fail(HLBM_E_INVALID, "member %d listed twice", i);
+  }
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  hlbm_status s;
+  for (int i = 0; i < count; ++i) {
+    if (modes[i] == HLBM_GROUP_PRIMAL_WINDOW && (s = ensure_window(lats[i])) != HLBM_OK) return s;
+    HIP_TRY(hipStreamSynchronize(lats[i]->stream));
+  }
+  const size_t ps = packed_primal_size(), as = packed_adjoint_size();
+  std::vector<unsigned char> tp, ta;
+  std::vector<int> fp, fa;
+  int bp = 0, ba = 0;
+  for (int i = 0; i < count; ++i) {
+    hlbm_lattice_s* L = lats[i];
+    const int blocks = tiles_x_of(L) * tiles_y_of(L) * L->desc.nz;
+    if (modes[i] == HLBM_GROUP_ADJOINT) {
+      ta.resize(ta.size() + as);
+      fill_packed_adjoint(L, ba, ta.data() + ta.size() - as);
+      fa.push_back(ba);
+      ba += blocks;
+    } else {
+      tp.resize(tp.size() + ps);
+      fill_packed_primal(L, modes[i] == HLBM_GROUP_PRIMAL_WINDOW, bp, tp.data() + tp.size() - ps);
+      fp.push_back(bp);
+      bp += blocks;
+    }
+  }
+  auto upload = [&](std::vector<unsigned char>& t, std::vector<int>& f, size_t esz, void** tab, int** first,
+                    size_t* cap) -> hlbm_status {
+    const size_t m = f.size();
+    if (m == 0) return HLBM_OK;
+    if (m > *cap) {
+      dev_free(*tab);
+      dev_free(*first);
+      *tab = nullptr;
+      *first = nullptr;
+      *cap = 0;
+      hlbm_status st;
+      if ((st = dev_alloc(tab, esz * m)) != HLBM_OK) return st;
+      if ((st = dev_alloc((void**)first, sizeof(int) * m)) != HLBM_OK) return st;
+      *cap = m;
+    }
+    HIP_TRY(hipMemcpyAsync(*tab, t.data(), esz * m, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(*first, f.data(), sizeof(int) * m, hipMemcpyHostToDevice, g->stream));
+    return HLBM_OK;
+  };
+  if ((s = upload(tp, fp, ps, &g->tab_primal, &g->first_primal, &g->cap_primal)) != HLBM_OK) return s;
+  if ((s = upload(ta, fa, as, &g->tab_adjoint, &g->first_adjoint, &g->cap_adjoint)) != HLBM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(g->stream));  // host tables go out of scope
+  delete[] g->members;
+  delete[] g->modes;
+  g->members = count ? new hlbm_lattice_s*[count] : nullptr;
+  g->modes = count ? new int32_t[count] : nullptr;
+  for (int i = 0; i < count; ++i) {
+    g->members[i] = lats[i];
+    g->modes[i] = modes[i];
+  }
+  g->count = count;
+  g->n_primal = (int)fp.size();
+  g->n_adjoint = (int)fa.size();
+  g->blocks_primal = bp;
+  g->blocks_adjoint = ba;
+  g->stencil = count ? lats[0]->desc.stencil : -1;
+  g->precision = count ? lats[0]->desc.precision : -1;
+  g->steps_since_set = 0;
+  return HLBM_OK;
+}
+
+extern "C" hlbm_status hlbm_group_step(hlbm_group g, int64_t n) {
+  if (!g) return fail(HLBM_E_INVALID, "null group");
+  if (n < 0) return fail(HLBM_E_INVALID, "negative step count");
+  for (int64_t k = 0; k < n; ++k) {
+    const int step = (int)((g->steps_since_set + k) & 1);
+    if (g->n_primal > 0)
+      HIP_TRY(launch_primal_packed(g->stream, g->stencil, g->precision, g->tab_primal, g->first_primal, g->n_primal,
+                                   g->blocks_primal, step));
+    if (g->n_adjoint > 0)
+      HIP_TRY(launch_adjoint_packed(g->stream, g->stencil, g->precision, g->tab_adjoint, g->first_adjoint,
+                                    g->n_adjoint, g->blocks_adjoint, step));
+  }
+  for (int i = 0; i < g->count; ++i) {
+    hlbm_lattice_s* L = g->members[i];
+    if (g->modes[i] == HLBM_GROUP_ADJOINT) {
+      L->adj_iters += n;
+      L->pvcur ^= (int)(n & 1);
+    } else {
+      L->parity ^= (int)(n & 1);
+      L->steps += n;
+      if (g->modes[i] == HLBM_GROUP_PRIMAL_WINDOW) L->nsamp += n;
+      L->adj_ready = 0;
+    }
+  }
+  g->steps_since_set += n;
+  return HLBM_OK;
+}
+
+extern "C" hlbm_status hlbm_group_synchronize(hlbm_group g) {
+  if (!g) return fail(HLBM_E_INVALID, "null group");
+  HIP_TRY(hipStreamSynchronize(g->stream));
   return HLBM_OK;
 }

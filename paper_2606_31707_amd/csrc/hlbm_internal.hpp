@@ -129,4 +129,33 @@ hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partial
 hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev);
 hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev);
 
+// packed launches over groups of lattices
+int tiles_x_of(const hlbm_lattice_s* L);
+int tiles_y_of(const hlbm_lattice_s* L);
+size_t packed_primal_size();
+size_t packed_adjoint_size();
+void fill_packed_primal(const hlbm_lattice_s* L, int accumulate, int first_block, void* out);
+void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out);
+hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
+                                int nm, int blocks, int step);
+hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
+                                 int nm, int blocks, int step);
+
 }  // namespace hlbm
+
+// A group of lattices stepped by packed launches (see hlbm_group_* in hlbm.h).
+struct hlbm_group_s {
+  hipStream_t stream = nullptr;
+  int stencil = -1, precision = -1;
+  int n_primal = 0, n_adjoint = 0;
+  int blocks_primal = 0, blocks_adjoint = 0;
+  void* tab_primal = nullptr;   // device tables
+  void* tab_adjoint = nullptr;
+  int* first_primal = nullptr;  // device first-block arrays
+  int* first_adjoint = nullptr;
+  size_t cap_primal = 0, cap_adjoint = 0;  // members the device tables hold
+  int64_t steps_since_set = 0;
+  hlbm_lattice_s** members = nullptr;
+  int32_t* modes = nullptr;
+  int count = 0;
+};

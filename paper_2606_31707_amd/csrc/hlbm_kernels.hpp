@@ -254,7 +254,8 @@ __device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
   const bool valid = (x < g.nx) && (y < g.ny);          \
   const int64_t cell = valid ? cell_of(g, x, y, z) : 0; \
   const bool inout = (g.bcx == BC_INOUT);               \
-  (void)inout;
+  (void)inout;                                          \
+  (void)cell;
 
 // =========================================================================
 // primal sweep (rows a3, a4, a5): HLBM-BGK collision (Eq. hlbm) toward
@@ -262,15 +263,16 @@ __device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
 // AA propagation with boundaries, fused FP64 window accumulation.
 // =========================================================================
 
+// One lattice update of cell (x, y, z) (inside the lattice).
 template <int Q, typename S, bool ODD, bool ACC>
-__global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const ObjBox ob,
-                                                S* __restrict__ A,
-                                                const typename Prec<S>::Dd* __restrict__ dpor,
-                                                S* __restrict__ ghost, const Acc acc) {
+__device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
+                                            const typename Prec<S>::Dd* __restrict__ dpor,
+                                            S* __restrict__ ghost, const Acc& acc, const int x, const int y,
+                                            const int z) {
   using L = Lat<Q>;
   using T = typename Prec<S>::T;
-  CELL_PROLOGUE
-  if (!valid) return;
+  const int64_t cell = cell_of(g, x, y, z);
+  const bool inout = (g.bcx == BC_INOUT);
   T s[Q];
   if (inout && x == 0) {  // pinned equilibrium inlet: not collided, source only
     inlet_state<Q, T>(g, y, s);
@@ -380,6 +382,66 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
         A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
       }
     }
+  }
+}
+
+template <int Q, typename S, bool ODD, bool ACC>
+__global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const ObjBox ob,
+                                                S* __restrict__ A,
+                                                const typename Prec<S>::Dd* __restrict__ dpor,
+                                                S* __restrict__ ghost, const Acc acc) {
+  CELL_PROLOGUE
+  if (!valid) return;
+  primal_cell<Q, S, ODD, ACC>(g, c, ob, A, dpor, ghost, acc, x, y, z);
+}
+
+// Packed launch: one workgroup grid covering several lattices of one stencil
+// and precision (member m owns blocks [first_block, first_block + tiles)).
+// Each member runs exactly the per-cell code of k_primal, so its result does
+// not depend on which other lattices share the launch.
+struct PackedPrimal {
+  Geo g;
+  Coll c;
+  ObjBox ob;
+  Acc acc;
+  void* A;
+  const void* dpor;
+  void* ghost;
+  int parity0;     // AA parity when the table was built
+  int accumulate;  // window accumulation on
+  int first_block, tiles_x, tiles_y, pad_;
+};
+
+__device__ __forceinline__ int packed_member(const int* __restrict__ first, int nm, int b) {
+  int m = 0;
+  while (m + 1 < nm && first[m + 1] <= b) ++m;
+  return m;
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __restrict__ tab,
+                                                       const int* __restrict__ first, int nm, int step) {
+  using Dd = typename Prec<S>::Dd;
+  const int b = blockIdx.x;
+  const PackedPrimal& P = tab[packed_member(first, nm, b)];
+  const int lb = b - P.first_block;
+  const int tx = lb % P.tiles_x, r = lb / P.tiles_x;
+  const int ty = r % P.tiles_y, z = r / P.tiles_y;
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
+  if (x >= P.g.nx || y >= P.g.ny) return;
+  S* A = (S*)P.A;
+  const Dd* dp = (const Dd*)P.dpor;
+  S* gh = (S*)P.ghost;
+  if ((P.parity0 + step) & 1) {
+    if (P.accumulate)
+      primal_cell<Q, S, true, true>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    else
+      primal_cell<Q, S, true, false>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+  } else {
+    if (P.accumulate)
+      primal_cell<Q, S, false, true>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    else
+      primal_cell<Q, S, false, false>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
   }
 }
 
@@ -786,16 +848,15 @@ __device__ __forceinline__ void adjoint_read_canonical(const Geo& g, const SA* _
 }
 
 template <int Q, typename SA, bool ODD>
-__global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, const AdjC ac,
-                                                 SA* __restrict__ A, const SA* __restrict__ prep,
-                                                 const double* __restrict__ src,
-                                                 const double* __restrict__ oprep,
-                                                 const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
+__device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, const AdjC& ac, SA* __restrict__ A,
+                                             const SA* __restrict__ prep, const double* __restrict__ src,
+                                             const double* __restrict__ oprep, const SA* __restrict__ pv_in,
+                                             SA* __restrict__ pv_out, const int x, const int y, const int z) {
   using L = Lat<Q>;
   using T = SA;
   constexpr int D = L::D;
-  CELL_PROLOGUE
-  if (!valid) return;
+  const int64_t cell = cell_of(g, x, y, z);
+  const bool inout = (g.bcx == BC_INOUT);
   if (inout && x == 0) {  // inlet: no dependence on the state, lambda = 0
     if (!ODD) {
 #pragma unroll
@@ -932,6 +993,50 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
       pv_out[k * g.gplane + vy + (int64_t)g.ny * vz] = lam[k];
     }
   }
+}
+
+template <int Q, typename SA, bool ODD>
+__global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, const AdjC ac,
+                                                 SA* __restrict__ A, const SA* __restrict__ prep,
+                                                 const double* __restrict__ src,
+                                                 const double* __restrict__ oprep,
+                                                 const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
+  CELL_PROLOGUE
+  if (!valid) return;
+  adjoint_cell<Q, SA, ODD>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z);
+}
+
+struct PackedAdjoint {
+  Geo g;
+  ObjBox ob;
+  AdjC ac;
+  void* A;
+  const void* prep;
+  const double* src;
+  const double* oprep;
+  void* pv[2];
+  int iter0;   // adjoint iterations done when the table was built
+  int pvcur0;  // outlet buffer holding the latest values at that time
+  int first_block, tiles_x, tiles_y, pad_;
+};
+
+template <int Q, typename SA>
+__global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __restrict__ tab,
+                                                        const int* __restrict__ first, int nm, int step) {
+  const int b = blockIdx.x;
+  const PackedAdjoint& P = tab[packed_member(first, nm, b)];
+  const int lb = b - P.first_block;
+  const int tx = lb % P.tiles_x, r = lb / P.tiles_x;
+  const int ty = r % P.tiles_y, z = r / P.tiles_y;
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
+  if (x >= P.g.nx || y >= P.g.ny) return;
+  const int cur = (P.pvcur0 + step) & 1;
+  const SA* pin = (const SA*)P.pv[cur];
+  SA* pout = (SA*)P.pv[cur ^ 1];
+  if ((P.iter0 + step) & 1)
+    adjoint_cell<Q, SA, true>(P.g, P.ob, P.ac, (SA*)P.A, (const SA*)P.prep, P.src, P.oprep, pin, pout, x, y, z);
+  else
+    adjoint_cell<Q, SA, false>(P.g, P.ob, P.ac, (SA*)P.A, (const SA*)P.prep, P.src, P.oprep, pin, pout, x, y, z);
 }
 
 // Residual: max |phi - snapshot| and max |phi| over the state cells.

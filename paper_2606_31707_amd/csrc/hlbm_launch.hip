@@ -316,3 +316,94 @@ hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev) {
 }
 
 }  // namespace hlbm
+
+// =========================================================================
+// packed launches (groups of small lattices)
+// =========================================================================
+
+namespace hlbm {
+
+int tiles_x_of(const hlbm_lattice_s* L) { return (L->desc.nx + BX - 1) / BX; }
+int tiles_y_of(const hlbm_lattice_s* L) { return (L->desc.ny + BY - 1) / BY; }
+
+void fill_packed_primal(const hlbm_lattice_s* L, int accumulate, int first_block, void* out) {
+  PackedPrimal* P = (PackedPrimal*)out;
+  P->g = make_geo(L);
+  P->c = make_coll(L);
+  P->c.probe_cell = -1;  // the probe is not recorded in packed launches
+  P->c.probe_out = nullptr;
+  P->ob = make_obj(L);
+  const bool smag = L->desc.smagorinsky_cs > 0.0;
+  P->acc = Acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
+               smag ? L->acc_tau : nullptr, L->acc_obj};
+  P->A = L->f;
+  P->dpor = L->dpor;
+  P->ghost = L->ghost;
+  P->parity0 = L->parity;
+  P->accumulate = accumulate;
+  P->first_block = first_block;
+  P->tiles_x = tiles_x_of(L);
+  P->tiles_y = tiles_y_of(L);
+  P->pad_ = 0;
+}
+
+void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out) {
+  PackedAdjoint* P = (PackedAdjoint*)out;
+  P->g = make_geo(L);
+  P->ob = make_obj(L);
+  P->ac.les = L->adj_les;
+  P->ac.diff = L->adj_diff;
+  P->ac.omega0 = L->adj_omega;
+  P->A = L->phi;
+  P->prep = L->prep;
+  P->src = L->src;
+  P->oprep = L->oprep;
+  P->pv[0] = L->pv[0];
+  P->pv[1] = L->pv[1];
+  P->iter0 = (int)(L->adj_iters & 1);
+  P->pvcur0 = L->pvcur;
+  P->first_block = first_block;
+  P->tiles_x = tiles_x_of(L);
+  P->tiles_y = tiles_y_of(L);
+  P->pad_ = 0;
+}
+
+size_t packed_primal_size() { return sizeof(PackedPrimal); }
+size_t packed_adjoint_size() { return sizeof(PackedAdjoint); }
+
+hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
+                                int nm, int blocks, int step) {
+  const dim3 grid((unsigned)blocks);
+  const PackedPrimal* t = (const PackedPrimal*)tab;
+  switch (stencil * 3 + precision) {
+    case 0: k_primal_packed<9, double><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 1: k_primal_packed<9, float><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 2: k_primal_packed<9, _Float16><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 3: k_primal_packed<19, double><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 4: k_primal_packed<19, float><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 5: k_primal_packed<19, _Float16><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
+                                 int nm, int blocks, int step) {
+  const dim3 grid((unsigned)blocks);
+  const PackedAdjoint* t = (const PackedAdjoint*)tab;
+  const bool f64 = precision == HLBM_FP64;
+  if (stencil == HLBM_D2Q9) {
+    if (f64)
+      k_adjoint_packed<9, double><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+    else
+      k_adjoint_packed<9, float><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+  } else {
+    if (f64)
+      k_adjoint_packed<19, double><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+    else
+      k_adjoint_packed<19, float><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

@@ -37,8 +37,11 @@ EXPORTS = [
     "hlbm_window_count", "hlbm_get_objective", "hlbm_solve_adjoint", "hlbm_get_gradient",
     "hlbm_get_adjoint", "hlbm_get_field", "hlbm_synchronize", "hlbm_profile_enable",
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
-    "hlbm_set_probe", "hlbm_get_probe",
+    "hlbm_set_probe", "hlbm_get_probe", "hlbm_reconfigure", "hlbm_group_create", "hlbm_group_destroy",
+    "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize",
 ]
+
+GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
 
 PROFILE_PRIMAL, PROFILE_PRIMAL_WINDOW, PROFILE_ADJOINT = 0, 1, 2
 
@@ -130,6 +133,12 @@ def load_library(path: str = LIB_PATH):
         "hlbm_profile_enable": (i32, [vp, i32]),
         "hlbm_profile_get": (i32, [vp, i32, P(dbl), P(i64)]),
         "hlbm_set_probe": (i32, [vp, i32, i32, i32, i64]),
+        "hlbm_reconfigure": (i32, [vp, dbl, dbl, dbl]),
+        "hlbm_group_create": (i32, [vp, P(vp)]),
+        "hlbm_group_destroy": (None, [vp]),
+        "hlbm_group_set": (i32, [vp, P(vp), P(i32), i32]),
+        "hlbm_group_step": (i32, [vp, i64]),
+        "hlbm_group_synchronize": (i32, [vp]),
         "hlbm_get_probe": (i32, [vp, vp, i64, P(i64)]),
         "hlbm_bytes_per_update": (i32, [vp, P(dbl), P(dbl), P(dbl)]),
         "hlbm_status_string": (C.c_char_p, [i32]),
@@ -344,7 +353,44 @@ class Lattice:
         _check(self._lib.hlbm_get_probe(self._h, out.ctypes.data_as(C.c_void_p), cap, C.byref(cnt)))
         return out[: cnt.value].copy()
 
+    def reconfigure(self, tau, cs, u_in):
+        _check(self._lib.hlbm_reconfigure(self._h, tau, cs, u_in))
+        self.desc.tau, self.desc.smagorinsky_cs, self.desc.u_in = tau, cs, u_in
+
     def bytes_per_update(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()
         _check(self._lib.hlbm_bytes_per_update(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"primal": a.value, "primal_window": b.value, "adjoint": c.value}
+
+
+class Group:
+    """Packed launches over several lattices of one stencil and precision."""
+
+    def __init__(self, stream=None):
+        self._lib = load_library()
+        h = C.c_void_p()
+        _check(self._lib.hlbm_group_create(stream, C.byref(h)))
+        self._h = h
+        self.members = []
+
+    def set(self, lattices, modes):
+        n = len(lattices)
+        arr = (C.c_void_p * max(n, 1))(*[L._h.value for L in lattices])
+        md = (C.c_int32 * max(n, 1))(*modes)
+        _check(self._lib.hlbm_group_set(self._h, arr, md, n))
+        self.members = list(lattices)
+
+    def step(self, n):
+        _check(self._lib.hlbm_group_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(self._lib.hlbm_group_synchronize(self._h))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.hlbm_group_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()

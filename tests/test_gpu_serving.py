@@ -1,0 +1,103 @@
+"""Packed launches and the serving loop on the GPU: a lattice stepped in a
+packed group gives the same bits as stepped by its own launches, FP64 members
+match the oracle, and a query's gradient is the same alone and in a mix."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_31707_amd import serving as S
+from tests.pairs import Spec, make_oracle, rel_err, say, state_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def _lat(H, nx, ny, prec, tau=0.6, seed=0, stream=None):
+    G = H.Lattice(stencil=H.D2Q9, precision=prec, nx=nx, ny=ny, tau=tau, u_in=0.05, stream=stream)
+    rng = np.random.default_rng(seed)
+    G.build_cylinder(nx / 4, (ny - 1) / 2, ny / 4, noise=rng.uniform(0, 0.05, nx * ny), noise_mode=H.NOISE_BOX,
+                     box_half=ny / 2)
+    G.init_equilibrium()
+    G.set_objective(H.OBJ_DISS, (2, 0, 0), (nx - 3, ny - 1, 0))
+    return G
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_group_steps_equal_individual_launches(prec):
+    from paper_2606_31707_amd import hlbm as H
+    say("group vs individual", prec)
+    shapes = [(130, 66), (64, 32), (200, 90)]
+    solo = [_lat(H, nx, ny, prec, seed=i) for i, (nx, ny) in enumerate(shapes)]
+    pack = [_lat(H, nx, ny, prec, seed=i) for i, (nx, ny) in enumerate(shapes)]
+    for L in solo:
+        L.run_primal(300)
+        L.run_primal(101, accumulate=True)
+    g = H.Group()
+    g.set(pack, [H.GROUP_PRIMAL] * 3)
+    g.step(300)
+    g.set(pack, [H.GROUP_PRIMAL_WINDOW] * 3)
+    g.step(101)
+    g.synchronize()
+    for a, b in zip(solo, pack):
+        assert np.array_equal(a.populations(), b.populations())
+        assert a.window_objective() == b.window_objective()
+    for L in solo:
+        L.solve_adjoint(H.SOURCE_MEAN, max_iters=200)
+    for L in pack:
+        L.solve_adjoint(H.SOURCE_MEAN, max_iters=0)
+    g.set(pack, [H.GROUP_ADJOINT] * 3)
+    g.step(200)
+    g.synchronize()
+    for a, b in zip(solo, pack):
+        assert np.array_equal(a.adjoint(), b.adjoint())
+        assert np.array_equal(a.gradient(), b.gradient())
+
+
+def test_group_member_matches_oracle_fp64():
+    from paper_2606_31707_amd import hlbm as H
+    say("group vs oracle")
+    s = Spec(nx=150, ny=41, tau=0.6, u_in=0.05, cyl=(37.5, 20.0, 10.25), obj=(O.OBJ_FFA, (100, 0, 0), (100, 40, 0), 0.05))
+    L = make_oracle(s)
+    G = H.Lattice(nx=150, ny=41, tau=0.6, u_in=0.05)
+    G.build_cylinder(37.5, 20.0, 10.25)
+    G.init_equilibrium()
+    G.set_objective(H.OBJ_FFA, (100, 0, 0), (100, 40, 0), u0=0.05)
+    other = _lat(H, 96, 48, 0, seed=5)
+    grp = H.Group()
+    grp.set([other, G], [H.GROUP_PRIMAL, H.GROUP_PRIMAL])
+    grp.step(500)
+    grp.synchronize()
+    L.step(500)
+    assert rel_err(G.populations(), L.populations(), state_mask(s)) < 1e-12
+    G.set_populations(L.populations())
+    L.adjoint_prepare(0)
+    L.adjoint_iterate(300)
+    G.solve_adjoint(H.SOURCE_STEADY, max_iters=0)
+    grp.set([G, other], [H.GROUP_ADJOINT, H.GROUP_PRIMAL])
+    grp.step(300)
+    grp.synchronize()
+    assert rel_err(G.gradient(), L.gradient()) < 1e-12
+
+
+def _server():
+    return S.Server(S.GPUBackend(pack_max_cells=300_000), mem_cap_bytes=8 << 30, max_slots=16, tick=256)
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    say("alone vs mix")
+    probe_small = S.Query(0, S.D2Q9, 160, 80, 1, 90.0, S.OBJ_DISS, 777)
+    probe_big = S.Query(1, S.D2Q9, 1024, 512, 1, 35.0, S.OBJ_FFA, 778)  # above the packing limit
+    mix = S.poisson_mix(10, rate=1e9, seed=5)
+    mix = [m for m in mix if m.stencil == S.D2Q9 and m.nx <= 512]
+    for i, m in enumerate(mix):
+        m.qid = 10 + i
+        m.arrival = 0.0
+    alone = {}
+    for pq in (probe_small, probe_big):
+        st = _server().run([pq], realtime=False)
+        alone[pq.qid] = st.results[0]
+    st = _server().run(mix[:3] + [probe_small] + mix[3:] + [probe_big], realtime=False)
+    got = {r.qid: r for r in st.results}
+    for qid in (0, 1):
+        assert got[qid].J == alone[qid].J
+        assert np.array_equal(got[qid].grad, alone[qid].grad), qid
+    assert len(st.results) == len(mix) + 2
