@@ -31,8 +31,8 @@ from paper_2606_31707_amd import hlbm as H  # noqa: E402
 from paper_2606_31707_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_31707_amd", "csrc", f)
-                  for f in ("hlbm_device.hpp", "hlbm_kernels.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_31707_amd", f)
+                  for f in ("csrc/hlbm_device.hpp", "csrc/hlbm_kernels.hpp", "build.py")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_primal_d2q9_fp64_vortex_re100_traffic.json")
 
 
@@ -124,7 +124,8 @@ def cpu_baseline(w: I.Workload, primal_steps: int, adj_iters: int):
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the device code (the counters are tied to it)."""
+    """SHA-256 over the device code and its build flags (the counters are
+    tied to them)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
@@ -141,6 +142,99 @@ def traffic_for(kernel_hash: str):
     if rec.get("kernel_source_sha256") != kernel_hash:
         return None
     return rec.get("bytes_per_launch")
+
+
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv -- "
+             "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 20000 "
+             "--adjoint-max 6000",
+    "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/FETCH_SIZE -o bench --output-format csv -- "
+                  "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 400 "
+                  "--adjoint-max 100 --profile-every 0",
+    "WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/WRITE_SIZE -o bench --output-format csv -- "
+                  "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 400 "
+                  "--adjoint-max 100 --profile-every 0",
+    "copy_FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copy_FETCH_SIZE -o copy --output-format csv "
+                       "-- python3 bench.py --copy-calibration-mib 512",
+    "copy_WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_WRITE_SIZE -o copy --output-format csv "
+                       "-- python3 bench.py --copy-calibration-mib 512",
+}
+PRIMAL_EVEN = "hlbm::k_primal<9, double, false, false>"
+PRIMAL_ODD = "hlbm::k_primal<9, double, true, false>"
+
+
+def summarize_profiles(d: str):
+    """Writes the kernel-trace table and the counter-traffic record of the
+    benchmark's dominant kernel from the rocprofv3 CSV output under `d`
+    (made by the PROFILE_CMDS commands)."""
+    import csv
+
+    def rows(path):
+        with open(path, newline="") as fh:
+            return list(csv.DictReader(fh))
+
+    def short(name):
+        name = name.replace("void ", "", 1)
+        return name.split("(")[0] if name.startswith("hlbm::") else name.split("(")[0][:60]
+
+    stats = rows(os.path.join(d, "trace", "bench_kernel_stats.csv"))
+    w = I.vortex_re100()
+    us = {short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in stats}
+    mean_us = 0.5 * (us[PRIMAL_EVEN] + us[PRIMAL_ODD])
+    lines = ["# Kernel trace: vortex_re100 (1100x410, D2Q9, FP64) gradient query", "",
+             "Command (run from the repository root on the MI355X box, `export TMPDIR=/tmp`):", "", "```",
+             PROFILE_CMDS["trace"], "```", "",
+             "Same query as the benchmark with 20 000 primal steps (window = last 20 %) and 6 000 adjoint "
+             "iterations, so the trace stays small; per-launch durations do not depend on the step count.", "",
+             "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    alg = 152 * w.n
+    lines += ["", f"Dominant kernel `k_primal<9,double,*,false>`: mean of the even and odd AA steps = "
+                  f"{mean_us:.2f} us per launch; 152 algorithmic B/LU x {w.n} cells / that duration = "
+                  f"{alg / mean_us / 1e3:.0f} GB/s ({alg / mean_us / 1e3 / HBM_PEAK_GBS * 100:.1f} % of 8 TB/s)."]
+
+    def per_launch(sub, counter):
+        vals = {PRIMAL_EVEN: [], PRIMAL_ODD: []}
+        for r in rows(os.path.join(d, sub, "bench_counter_collection.csv")):
+            k = short(r["Kernel_Name"])
+            if k in vals and r["Counter_Name"] == counter:
+                vals[k].append(float(r["Counter_Value"]))
+        return {"even": float(np.mean(vals[PRIMAL_EVEN])), "odd": float(np.mean(vals[PRIMAL_ODD]))}
+
+    def copy_kib(sub, counter):
+        v = [float(r["Counter_Value"]) for r in rows(os.path.join(d, sub, "copy_counter_collection.csv"))
+             if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return float(np.mean(v))
+
+    fetch, write = per_launch("FETCH_SIZE", "FETCH_SIZE"), per_launch("WRITE_SIZE", "WRITE_SIZE")
+    cf, cw = copy_kib("copy_FETCH_SIZE", "FETCH_SIZE"), copy_kib("copy_WRITE_SIZE", "WRITE_SIZE")
+    ff, wf = 512 * 1024 / cf, 512 * 1024 / cw
+    rd = 0.5 * (fetch["even"] + fetch["odd"]) * ff * 1024
+    wr = 0.5 * (write["even"] + write["odd"]) * wf * 1024
+    rec = {
+        "kernel": "k_primal<9, double, *, false> (AA even + odd, no window), 1100x410 vortex_re100",
+        "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
+        "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 512 MiB)", "fetch_kib": cf,
+                        "write_kib": cw, "fetch_factor": ff, "write_factor": wf},
+        "bytes_per_launch": rd + wr, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+        "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (rd + wr) / alg,
+        "kernel_source_sha256": kernel_source_hash(),
+        "commands": [PROFILE_CMDS[k] for k in ("FETCH_SIZE", "WRITE_SIZE", "copy_FETCH_SIZE", "copy_WRITE_SIZE")],
+    }
+    lines += ["", "Counter traffic per launch of the same kernel (rocprofv3 `--pmc FETCH_SIZE`, then "
+                  "`--pmc WRITE_SIZE`, each scaled by the value the counter reads for a plain 512 MiB device "
+                  f"copy: x{ff:.3f} and x{wf:.3f}); commands in `{os.path.basename(TRAFFIC_FILE)}`.",
+              f"Reads {rd / 1e6:.1f} MB (algorithmic {(9 * 8 + 8) * w.n / 1e6:.1f} MB: 9 populations + "
+              f"porosity), writes {wr / 1e6:.1f} MB (algorithmic {9 * 8 * w.n / 1e6:.1f} MB)."]
+    with open(os.path.join(ROOT, "profiles", "k_primal_d2q9_fp64_vortex_re100.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({"us_per_launch": mean_us, "traffic_bytes_per_launch": rd + wr,
+                      "traffic_over_algorithmic": (rd + wr) / alg}))
 
 
 def report_differentiation(n_fields: int, fd_fields: int, fd_dirs: int):
@@ -249,10 +343,15 @@ def main():
     ap.add_argument("--mem-cap-gib", type=float, default=16.0)
     ap.add_argument("--tick", type=int, default=256)
     ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="write the profiles/ summaries from the rocprofv3 output under DIR and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
+    if args.profile_summary:
+        summarize_profiles(args.profile_summary)
+        return
     if args.report == "differentiation":
         report_differentiation(args.fields, args.fd_fields, args.fd_directions)
         return

@@ -16,6 +16,9 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "hipcc", "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-shared",
         "-Wall", "-Wno-unused-function",
+        # multiply-adds fused per source expression only, so the same inlined
+        # per-cell code rounds identically in every kernel that contains it
+        "-ffp-contract=on",
         # no packed FP32 instructions in device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-o", LIB_PATH + ".tmp",

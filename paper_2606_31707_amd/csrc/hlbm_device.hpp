@@ -16,8 +16,17 @@ enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_INOUT = 2 };
 enum { OBJ_FFA = 0, OBJ_DISS = 1, OBJ_MOMENTUM = 2 };
 enum { NB_CELL = 0, NB_BOUNCE = 1, NB_OUTLET = 2, NB_DROP = 3 };
 
-constexpr int BX = 64;  // one wavefront along x: 64 consecutive cells per load
-constexpr int BY = 4;   // four rows per 256-thread workgroup
+#ifndef HLBM_TILE_BX
+#define HLBM_TILE_BX 128
+#endif
+#ifndef HLBM_XCD_REMAP
+#define HLBM_XCD_REMAP 1
+#endif
+// 128 x 2 tiles: measured best for the FP64 sweeps (within 2-3 % of 64 x 4 and
+// 256 x 1 for every stencil and precision).
+constexpr int BX = HLBM_TILE_BX;   // wavefronts along x: BX consecutive cells per row
+constexpr int BY = 256 / BX;       // rows per 256-thread workgroup
+constexpr int NXCD = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 
 // ---- velocity sets (Sec. 2.1: D2Q9 and D3Q19) ------------------------------
 template <int Q>
@@ -82,6 +91,7 @@ struct Prec<_Float16> {
 // ---- geometry and boundary classification ---------------------------------
 struct Geo {
   int nx, ny, nz;
+  int tiles_x, tiles_y;  // BX x BY tiles per row / per plane of the sweep grid
   int bcx, bcy, bcz;
   int64_t plane;   // population plane stride (elements)
   int64_t gplane;  // outlet (y, z) plane stride (elements)
@@ -164,6 +174,18 @@ __device__ __forceinline__ double block_max256(double v, double* lds) {
   if (t == 0) r = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
   __syncthreads();
   return r;
+}
+
+// The sweeps run on a 1D grid of BX x BY tiles.  Workgroups are dispatched
+// round-robin over the XCDs, each with its own L2; renumbering them so that
+// XCD k takes one contiguous range of tiles (row-major) keeps x-neighbouring
+// tiles, whose odd-step pulls and pushes share the cache lines at the tile
+// edges, in the same L2.  b -> tile is a bijection of [0, nt).
+__device__ __forceinline__ int sweep_tile(int b, int nt) {
+  if (!HLBM_XCD_REMAP) return b;
+  const int q = nt / NXCD, r = nt % NXCD;
+  const int xcd = b % NXCD, k = b / NXCD;
+  return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
 __device__ __forceinline__ int linear_block() {

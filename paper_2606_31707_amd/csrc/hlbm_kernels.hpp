@@ -247,6 +247,19 @@ __device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
   }
 }
 
+// Sweep kernels: 1D grid over the tiles (see sweep_tile).
+#define SWEEP_PROLOGUE                                                       \
+  const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x);                \
+  const int z = t_ / (g.tiles_x * g.tiles_y);                                \
+  const int r_ = t_ - z * g.tiles_x * g.tiles_y;                             \
+  const int x = (r_ % g.tiles_x) * BX + threadIdx.x;                         \
+  const int y = (r_ / g.tiles_x) * BY + threadIdx.y;                         \
+  const bool valid = (x < g.nx) && (y < g.ny);                               \
+  const int64_t cell = valid ? cell_of(g, x, y, z) : 0;                      \
+  const bool inout = (g.bcx == BC_INOUT);                                    \
+  (void)inout;                                                               \
+  (void)cell;
+
 #define CELL_PROLOGUE                                   \
   const int x = blockIdx.x * BX + threadIdx.x;          \
   const int y = blockIdx.y * BY + threadIdx.y;          \
@@ -390,7 +403,7 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
                                                 S* __restrict__ A,
                                                 const typename Prec<S>::Dd* __restrict__ dpor,
                                                 S* __restrict__ ghost, const Acc acc) {
-  CELL_PROLOGUE
+  SWEEP_PROLOGUE
   if (!valid) return;
   primal_cell<Q, S, ODD, ACC>(g, c, ob, A, dpor, ghost, acc, x, y, z);
 }
@@ -422,7 +435,7 @@ template <int Q, typename S>
 __global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __restrict__ tab,
                                                        const int* __restrict__ first, int nm, int step) {
   using Dd = typename Prec<S>::Dd;
-  const int b = blockIdx.x;
+  const int b = sweep_tile((int)blockIdx.x, (int)gridDim.x);
   const PackedPrimal& P = tab[packed_member(first, nm, b)];
   const int lb = b - P.first_block;
   const int tx = lb % P.tiles_x, r = lb / P.tiles_x;
@@ -1001,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
                                                  const double* __restrict__ src,
                                                  const double* __restrict__ oprep,
                                                  const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
-  CELL_PROLOGUE
+  SWEEP_PROLOGUE
   if (!valid) return;
   adjoint_cell<Q, SA, ODD>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z);
 }
@@ -1023,7 +1036,7 @@ struct PackedAdjoint {
 template <int Q, typename SA>
 __global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __restrict__ tab,
                                                         const int* __restrict__ first, int nm, int step) {
-  const int b = blockIdx.x;
+  const int b = sweep_tile((int)blockIdx.x, (int)gridDim.x);
   const PackedAdjoint& P = tab[packed_member(first, nm, b)];
   const int lb = b - P.first_block;
   const int tx = lb % P.tiles_x, r = lb / P.tiles_x;

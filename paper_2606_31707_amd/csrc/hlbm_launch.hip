@@ -23,6 +23,8 @@ Geo make_geo(const hlbm_lattice_s* L) {
   g.nx = L->desc.nx;
   g.ny = L->desc.ny;
   g.nz = L->desc.nz;
+  g.tiles_x = (g.nx + BX - 1) / BX;
+  g.tiles_y = (g.ny + BY - 1) / BY;
   g.bcx = L->desc.bc_x;
   g.bcy = L->desc.bc_y;
   g.bcz = L->desc.stencil == HLBM_D2Q9 ? BC_PERIODIC : L->desc.bc_z;
@@ -70,6 +72,12 @@ dim3 cell_grid(const hlbm_lattice_s* L) {
 
 static const dim3 kBlock(BX, BY, 1);
 
+// 1D grid of the sweep kernels (k_primal, k_adjoint): one workgroup per tile.
+static dim3 sweep_grid(const hlbm_lattice_s* L) {
+  const dim3 c = cell_grid(L);
+  return dim3(c.x * c.y * c.z, 1, 1);
+}
+
 template <int Q, typename S>
 static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
   using Dd = typename Prec<S>::Dd;
@@ -81,7 +89,7 @@ static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, 
   S* A = (S*)L->f;
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
-  const dim3 grid = cell_grid(L);
+  const dim3 grid = sweep_grid(L);
   if (L->parity == 0) {
     if (accumulate)
       launch_k(k_primal<Q, S, false, true>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
@@ -271,10 +279,10 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   SA* pout = (SA*)L->pv[L->pvcur ^ 1];
   const SA* prep = (const SA*)L->prep;
   if ((L->adj_iters & 1) == 0)
-    launch_k(k_adjoint<Q, SA, false>, cell_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
+    launch_k(k_adjoint<Q, SA, false>, sweep_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
              L->oprep, pin, pout);
   else
-    launch_k(k_adjoint<Q, SA, true>, cell_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
+    launch_k(k_adjoint<Q, SA, true>, sweep_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
              L->oprep, pin, pout);
   return hipGetLastError();
 }

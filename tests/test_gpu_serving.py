@@ -22,14 +22,10 @@ def _lat(H, nx, ny, prec, tau=0.6, seed=0, stream=None):
 
 
 def _same(a, b, prec):
-    """Bitwise for FP32/FP16S.  In FP64 the packed and the individual kernels
-    are separate compilations of the same inlined per-cell code and may
-    contract multiply-adds differently: rounding-level agreement only (the
-    serving loop always routes a query the same way, so its results are
-    bitwise reproducible regardless)."""
-    if prec != 0:
-        return np.array_equal(a, b)
-    return np.abs(a - b).max() <= 1e-13 * max(np.abs(b).max(), 1e-300)
+    """Bitwise in every precision: the packed and the individual kernels run
+    the same inlined per-cell code, and multiply-adds are fused per source
+    expression only (-ffp-contract=on), so both round identically."""
+    return np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
