@@ -319,6 +319,107 @@ def report_serving(n: int, rate: float, cap_gib: float, tick: int, slots: int):
     print(json.dumps(out), flush=True)
 
 
+def report_les(spinup: int, window: int, adj_iters: int, forms):
+    """The 3D LES case (768 x 384 x 128 D3Q19, Smagorinsky C_S = 0.1, Re 3900,
+    drag plane): FP32, FP16-shifted and FP64 population storage with FP64
+    window accumulation; the mean flow of each form against the FP64 form
+    beside its own statistical error (difference of the two window halves);
+    mean-flow drag adjoints with the frozen (FTA) and the differentiated
+    closure, tau_adj in {tau0, 0.6}; sweep rates."""
+    w = I.les_re3900()
+    names = {H.FP64: "fp64", H.FP32: "fp32", H.FP16S: "fp16s"}
+    res, means, grads = {}, {}, {}
+    chunk = 2000
+
+    def l2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def cos(a, b):
+        return float(a @ b / np.linalg.norm(a) / np.linalg.norm(b))
+
+    for prec in forms:
+        name = names[prec]
+        diff = prec == H.FP32  # the differentiated closure needs the full mean populations
+        t0 = time.perf_counter()
+        G = H.Lattice(stencil=w.stencil, precision=prec, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
+                      bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
+                      u_in=w.u_max, track_mean_populations=diff)
+        G.build_cylinder(w.xc, w.yc, w.D)
+        G.init_equilibrium(1.0, I.initial_velocity(w))
+        G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
+        G.profile_enable(97)
+        r = {"track_mean_populations": diff}
+        ok = True
+        for done in range(0, spinup, chunk):
+            G.run_primal(min(chunk, spinup - done))
+            umax = float(np.abs(G.field(H.FIELD_U)[0]).max())
+            log(f"les {name}: step {done + chunk}, max u_x {umax:.4f} ({time.perf_counter() - t0:.0f} s)")
+            if not np.isfinite(umax) or umax > 0.4:
+                ok = False
+                break
+        r["stable"] = ok
+        if not ok:
+            res[name] = r
+            G.close()
+            continue
+        G.window_reset()
+        half = window // 2
+        for k in range(2):
+            for done in range(0, half, chunk):
+                G.run_primal(min(chunk, half - done), accumulate=True)
+                log(f"les {name}: window half {k}, step {done + chunk} ({time.perf_counter() - t0:.0f} s)")
+            if k == 0:
+                u_h1, J_h1 = G.field(H.FIELD_MEAN_U), G.window_objective()
+        u_all, J_all = G.field(H.FIELD_MEAN_U), G.window_objective()
+        u_h2, J_h2 = 2.0 * u_all - u_h1, 2.0 * J_all - J_h1
+        means[name] = u_all
+        r.update({"J_mean": J_all, "J_halves": [J_h1, J_h2], "mean_u_halves_rel_l2": l2(u_h1, u_h2),
+                  "J_halves_rel": abs(J_h1 - J_h2) / abs(J_all)})
+        variants = [("fta", H.TURB_FROZEN, 0.0), ("fta_tau0.6", H.TURB_FROZEN, 0.6)]
+        if diff:
+            variants += [("diff", H.TURB_DIFFERENTIATED, 0.0), ("diff_tau0.6", H.TURB_DIFFERENTIATED, 0.6)]
+        r["adjoint"] = {}
+        p = G.profile()
+        bpu = G.bytes_per_update()
+        r["sweeps"] = {k: {"us_per_launch": p[k]["mean_us"], "GLUPS": w.n / p[k]["mean_us"] / 1e3,
+                           "GB_s": bpu[k] * w.n / p[k]["mean_us"] / 1e3} for k in p if p[k]["sampled"]}
+        for vname, turb, tau_adj in variants:
+            ta = time.perf_counter()
+            G.profile_enable(97)
+            it, rr, _ = G.solve_adjoint(H.SOURCE_MEAN, tau_adj=tau_adj, turb=turb, max_iters=adj_iters,
+                                        tol=1e-8, check_every=1000)
+            g = G.gradient()
+            grads[(name, vname)] = g
+            pa, ba = G.profile()["adjoint"]["mean_us"], G.bytes_per_update()["adjoint"]
+            r["adjoint"][vname] = {"iters": it, "residual": rr, "seconds": time.perf_counter() - ta,
+                                   "max_abs_grad": float(np.abs(g).max()), "us_per_launch": pa,
+                                   "GB_s": ba * w.n / pa / 1e3 if pa > 0 else None}
+            log(f"les {name} adjoint {vname}: {it} it, residual {rr:.2e}")
+        r["seconds"] = time.perf_counter() - t0
+        res[name] = r
+        G.close()
+
+    ref = "fp64" if "fp64" in means else "fp32"
+    cmp = {}
+    for name in means:
+        if name == ref:
+            continue
+        c = {"mean_u_rel_l2_vs_" + ref: l2(means[name], means[ref]),
+             "J_mean_rel_vs_" + ref: abs(res[name]["J_mean"] - res[ref]["J_mean"]) / abs(res[ref]["J_mean"])}
+        if (ref, "fta") in grads and (name, "fta") in grads:
+            c["grad_fta_rel_l2_vs_" + ref] = l2(grads[(name, "fta")], grads[(ref, "fta")])
+            c["grad_fta_cosine_vs_" + ref] = cos(grads[(name, "fta")], grads[(ref, "fta")])
+        cmp[name] = c
+    if ("fp32", "diff") in grads:
+        g = grads
+        cmp["fp32_fta_vs_diff"] = {"cosine": cos(g[("fp32", "fta")], g[("fp32", "diff")]),
+                                   "rel_l2": l2(g[("fp32", "fta")], g[("fp32", "diff")]),
+                                   "cosine_tau0.6": cos(g[("fp32", "fta_tau0.6")], g[("fp32", "diff_tau0.6")])}
+    out = {"report": "les", "workload": w.name, "spinup_steps": spinup, "window_steps": window,
+           "adjoint_max_iters": adj_iters, "forms": res, "comparison": cmp}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,11 +434,15 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--report", choices=["differentiation", "serving"], default=None,
+    ap.add_argument("--report", choices=["differentiation", "serving", "les"], default=None,
                     help="print a secondary measurement report instead of the benchmark line")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--fd-fields", type=int, default=2)
     ap.add_argument("--fd-directions", type=int, default=8)
+    ap.add_argument("--les-spinup", type=int, default=30000)
+    ap.add_argument("--les-window", type=int, default=30000)
+    ap.add_argument("--les-adjoint", type=int, default=8000)
+    ap.add_argument("--les-forms", default="fp32,fp16s,fp64")
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--rate", type=float, default=2.0)
     ap.add_argument("--mem-cap-gib", type=float, default=16.0)
@@ -354,6 +459,11 @@ def main():
         return
     if args.report == "differentiation":
         report_differentiation(args.fields, args.fd_fields, args.fd_directions)
+        return
+    if args.report == "les":
+        forms = {"fp64": H.FP64, "fp32": H.FP32, "fp16s": H.FP16S}
+        report_les(args.les_spinup, args.les_window, args.les_adjoint,
+                   [forms[f] for f in args.les_forms.split(",")])
         return
     if args.report == "serving":
         report_serving(args.queries, args.rate, args.mem_cap_gib, args.tick, args.slots)
