@@ -420,6 +420,103 @@ def report_les(spinup: int, window: int, adj_iters: int, forms):
     print(json.dumps(out), flush=True)
 
 
+def report_validation3d(steps: int, adj_iters: int, fd_scale: float, fd_points: int):
+    """The steady 3D validation case (permeable cylinder, Re 40, D3Q19): FP64
+    and FP32 primal over T = 32 s, steady adjoints for the drag (FFA) and
+    dissipation objectives, FP32 against FP64 (objective, whole gradient field
+    and the cylinder-surface samples at mid-span), and central differences of
+    the converged FP64 objective on a scaled copy of the case."""
+    w = I.porous3d_re40()
+    box = w.extra["dissipation_box"]
+    objs = {"ffa": (H.OBJ_FFA, w.lo, w.hi), "diss": (H.OBJ_DISS, box[0], box[1])}
+    names = {H.FP64: "fp64", H.FP32: "fp32"}
+    R = 0.5 * w.D
+    x, y, z = np.arange(w.n) % w.nx, (np.arange(w.n) // w.nx) % w.ny, np.arange(w.n) // (w.nx * w.ny)
+    r = np.hypot(x - w.xc, y - w.yc)
+    ring = np.nonzero((np.abs(r - R) <= 0.5) & (z == w.nz // 2))[0]
+    ring = ring[np.argsort(np.arctan2(y[ring] - w.yc, x[ring] - w.xc))]
+    res, grads = {}, {}
+
+    def make(wl, prec):
+        G = H.Lattice(stencil=wl.stencil, precision=prec, nx=wl.nx, ny=wl.ny, nz=wl.nz, tau=wl.tau,
+                      bc_x=H.BC_INLET_OUTLET, bc_y=wl.bc_y, bc_z=wl.bc_z, inlet_profile=wl.inlet_profile,
+                      u_in=wl.u_max)
+        G.build_cylinder(wl.xc, wl.yc, wl.D, d_solid=wl.d_solid)
+        G.init_equilibrium()
+        return G
+
+    for prec in (H.FP64, H.FP32):
+        name = names[prec]
+        t0 = time.perf_counter()
+        G = make(w, prec)
+        G.set_objective(H.OBJ_FFA, w.lo, w.hi, u0=w.u0)
+        for done in range(0, steps - 1000, 5000):
+            G.run_primal(min(5000, steps - 1000 - done))
+            log(f"validation3d {name}: step {min(done + 5000, steps - 1000)} ({time.perf_counter() - t0:.0f} s)")
+        u1 = G.field(H.FIELD_U)
+        G.run_primal(1000)
+        u2 = G.field(H.FIELD_U)
+        r_ = {"steady_residual_per_1000": float(np.abs(u2 - u1).max() / np.abs(u2).max()),
+              "primal_seconds": time.perf_counter() - t0}
+        for oname, (kind, lo, hi) in objs.items():
+            G.set_objective(kind, lo, hi, u0=w.u0)
+            J = G.objective(0)
+            ta = time.perf_counter()
+            it, rr, _ = G.solve_adjoint(H.SOURCE_STEADY, max_iters=adj_iters, tol=1e-10, check_every=1000)
+            g = G.gradient()
+            grads[(name, oname)] = g
+            r_[oname] = {"J": J, "adjoint_iters": it, "adjoint_residual": rr,
+                         "adjoint_seconds": time.perf_counter() - ta,
+                         "surface_gradient": [float(v) for v in g[ring]]}
+            log(f"validation3d {name} {oname}: J {J:.9e}, adjoint {it} it, residual {rr:.2e}")
+        res[name] = r_
+        G.close()
+    cmp = {}
+    for oname in objs:
+        a, b = grads[("fp32", oname)], grads[("fp64", oname)]
+        cmp[oname] = {"J_rel": abs(res["fp32"][oname]["J"] - res["fp64"][oname]["J"]) / abs(res["fp64"][oname]["J"]),
+                      "grad_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                      "grad_cosine": float(a @ b / np.linalg.norm(a) / np.linalg.norm(b)),
+                      "surface_rel_max": float(np.abs(a[ring] - b[ring]).max() / np.abs(b[ring]).max())}
+
+    # central differences of the converged FP64 drag on a scaled copy
+    ws = I.scaled(w, fd_scale)
+    G = make(ws, H.FP64)
+    G.set_objective(H.OBJ_FFA, ws.lo, ws.hi, u0=ws.u0)
+    G.run_primal(400000, steady_tol=1e-13, check_every=500)
+    d0 = G.porosity()
+    f0 = G.populations()
+    J0 = G.objective(0)
+    G.solve_adjoint(H.SOURCE_STEADY, max_iters=400000, tol=1e-13, check_every=500)
+    g = G.gradient()
+    xs, ys, zs = np.arange(ws.n) % ws.nx, (np.arange(ws.n) // ws.nx) % ws.ny, np.arange(ws.n) // (ws.nx * ws.ny)
+    rs = np.hypot(xs - ws.xc, ys - ws.yc)
+    cand = np.nonzero((np.abs(rs - 0.5 * ws.D) <= 0.5) & (zs == ws.nz // 2) & (d0 > 2e-4) & (d0 < 1 - 2e-4))[0]
+    cand = cand[np.argsort(np.arctan2(ys[cand] - ws.yc, xs[cand] - ws.xc))]
+    pick = cand[np.linspace(0, len(cand) - 1, fd_points).astype(int)]
+    fd = []
+    eps = 1e-4
+    for c in pick:
+        vals = []
+        for sgn in (1.0, -1.0):
+            d = d0.copy()
+            d[c] += sgn * eps
+            G.set_porosity(d)
+            G.set_populations(f0)
+            G.run_primal(400000, steady_tol=1e-13, check_every=500)
+            vals.append(G.objective(0))
+        fdv = (vals[0] - vals[1]) / (2 * eps)
+        fd.append({"cell": int(c), "angle_deg": float(np.degrees(np.arctan2(ys[c] - ws.yc, xs[c] - ws.xc))),
+                   "adjoint": float(g[c]), "fd": fdv, "rel_err": abs(g[c] - fdv) / abs(fdv)})
+        log(f"validation3d FD cell {c}: adjoint {g[c]:.9e}, FD {fdv:.9e}")
+    G.close()
+    out = {"report": "validation3d", "workload": w.name, "steps": steps, "d_solid": w.d_solid,
+           "surface_samples": len(ring), "forms": res, "fp32_vs_fp64": cmp,
+           "fd": {"workload": ws.name, "cells": ws.n, "J": J0, "eps": eps, "points": fd,
+                  "max_rel_err": max(p_["rel_err"] for p_ in fd)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,7 +531,7 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--report", choices=["differentiation", "serving", "les"], default=None,
+    ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d"], default=None,
                     help="print a secondary measurement report instead of the benchmark line")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--fd-fields", type=int, default=2)
@@ -443,6 +540,10 @@ def main():
     ap.add_argument("--les-window", type=int, default=30000)
     ap.add_argument("--les-adjoint", type=int, default=8000)
     ap.add_argument("--les-forms", default="fp32,fp16s,fp64")
+    ap.add_argument("--v3d-steps", type=int, default=42336)
+    ap.add_argument("--v3d-adjoint", type=int, default=60000)
+    ap.add_argument("--v3d-fd-scale", type=float, default=1.0 / 3.0)
+    ap.add_argument("--v3d-fd-points", type=int, default=4)
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--rate", type=float, default=2.0)
     ap.add_argument("--mem-cap-gib", type=float, default=16.0)
@@ -464,6 +565,9 @@ def main():
         forms = {"fp64": H.FP64, "fp32": H.FP32, "fp16s": H.FP16S}
         report_les(args.les_spinup, args.les_window, args.les_adjoint,
                    [forms[f] for f in args.les_forms.split(",")])
+        return
+    if args.report == "validation3d":
+        report_validation3d(args.v3d_steps, args.v3d_adjoint, args.v3d_fd_scale, args.v3d_fd_points)
         return
     if args.report == "serving":
         report_serving(args.queries, args.rate, args.mem_cap_gib, args.tick, args.slots)

@@ -166,10 +166,15 @@ hlbm_status hlbm_set_porosity(hlbm_lattice lat, const double* d, int64_t n, int3
  * for R-1 < r < R+1, 0 beyond; d = 1 - chi (Sec. 5.1: d = 0 in the cylinder).
  * noise[n] (may be NULL) holds caller-drawn values: RIM adds them to d where
  * 0 < chi < 1, BOX adds them to chi where |x-xc|, |y-yc| <= box_half; both
- * clamp to [0, 1]. */
+ * clamp to [0, 1].  d_solid in [0, 1) is the porosity inside a permeable
+ * cylinder (Sec. 2.1: d = 1 - dx^2 tau nu / K for permeability K; the
+ * validation cases of Sec. 5.2 use K = 1e-6 m^2): the final field is
+ * 1 - (1 - d)(1 - d_solid), i.e. d unchanged for d_solid = 0.
+ * Errors: INVALID (non-finite centre, D <= 0, d_solid outside [0, 1), bad
+ * noise mode or length), DEVICE. */
 hlbm_status hlbm_build_cylinder(hlbm_lattice lat, double xc, double yc, double D,
                                 const double* noise, int64_t n, int32_t mem,
-                                int32_t noise_mode, double box_half);
+                                int32_t noise_mode, double box_half, double d_solid);
 /* f_i = f_i^eq(rho0, d u) with u[3n] (component-major) or, if u is NULL, the
  * inlet profile continued into the domain (INLET_OUTLET) or rest.  Resets the
  * step parity, the window and the adjoint. */

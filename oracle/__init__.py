@@ -62,7 +62,8 @@ def _load():
         "orc_n": (C.c_long, [vp]),
         "orc_set_porosity": (C.c_int, [vp, _DP]),
         "orc_get_porosity": (C.c_int, [vp, _DP]),
-        "orc_build_cylinder": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, vp, C.c_int, C.c_double]),
+        "orc_build_cylinder": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, vp, C.c_int, C.c_double,
+                                         C.c_double]),
         "orc_init_equilibrium": (C.c_int, [vp, C.c_double, vp]),
         "orc_set_populations": (C.c_int, [vp, _DP]),
         "orc_get_populations": (C.c_int, [vp, _DP]),
@@ -252,9 +253,9 @@ class Lattice:
         self._lib.orc_get_porosity(self._h, d)
         return d
 
-    def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0):
+    def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0, d_solid=0.0):
         nz = None if noise is None else _f64(np.ravel(noise))
-        self._lib.orc_build_cylinder(self._h, xc, yc, D, _ptr(nz), noise_mode, box_half)
+        self._lib.orc_build_cylinder(self._h, xc, yc, D, _ptr(nz), noise_mode, box_half, d_solid)
 
     def init_equilibrium(self, rho0=1.0, u=None):
         ua = None if u is None else _f64(np.reshape(u, (3, self.n)))

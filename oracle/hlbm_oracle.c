@@ -613,7 +613,7 @@ int orc_get_porosity(const orc_lattice* L, double* d) {
  * chi = (1 + cos(pi (r - R + 1)/2))/2 on R-1 < r < R+1, 0 outside; d = 1 - chi
  * (Sec. 5.1: d = 0 in the cylinder, d = 1 in the fluid). */
 int orc_build_cylinder(orc_lattice* L, double xc, double yc, double D, const double* noise,
-                       int noise_mode, double box_half) {
+                       int noise_mode, double box_half, double d_solid) {
   const double pi = 3.14159265358979323846;
   double R = 0.5 * D;
   for (long c = 0; c < L->n; ++c) {
@@ -640,6 +640,9 @@ int orc_build_cylinder(orc_lattice* L, double xc, double yc, double D, const dou
       if (ch > 1.0) ch = 1.0;
       d = 1.0 - ch;
     }
+    /* permeable cylinder: porosity d_solid where chi = 1 (d_solid = 0 leaves
+       d untouched) */
+    if (d_solid != 0.0) d = 1.0 - (1.0 - d) * (1.0 - d_solid);
     L->d[c] = d;
   }
   L->adj_ready = 0;

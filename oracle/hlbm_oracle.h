@@ -64,9 +64,11 @@ int orc_get_porosity(const orc_lattice* L, double* d);
 /* Cylinder of diameter D centred at (xc, yc), axis along z, cosine ramp over
  * [R-1, R+1]; noise (one value per cell, drawn by the caller) is applied per
  * noise_mode: RIM adds it to d on cells with 0 < chi < 1, BOX adds it to chi
- * on cells with |x-xc|,|y-yc| <= box_half; both clamp to [0,1]. */
+ * on cells with |x-xc|,|y-yc| <= box_half; both clamp to [0,1].  A permeable
+ * cylinder (Sec. 2.1, d = 1 - dx^2 tau nu / K inside) has porosity d_solid
+ * in its core: d <- 1 - (1 - d)(1 - d_solid). */
 int orc_build_cylinder(orc_lattice* L, double xc, double yc, double D,
-                       const double* noise, int noise_mode, double box_half);
+                       const double* noise, int noise_mode, double box_half, double d_solid);
 
 /* f_i = f_i^eq(rho0, d*u); u is 3*n component-major or NULL (NULL: the inlet
  * profile continued into the domain for inlet/outlet channels, else 0). */

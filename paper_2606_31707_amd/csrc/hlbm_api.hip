@@ -293,7 +293,7 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
   if (hipMemsetAsync(L->ghost, 0, L->ssize * L->q * L->gplane, L->stream) != hipSuccess)
     return bail(fail(HLBM_E_DEVICE, "memset failed"));
   // d = 1 everywhere: a cylinder of negative diameter leaves chi = 0
-  if (launch_cylinder(L, 0.0, 0.0, -10.0, nullptr, 0, 0.0) != hipSuccess)
+  if (launch_cylinder(L, 0.0, 0.0, -10.0, nullptr, 0, 0.0, 0.0) != hipSuccess)
     return bail(fail(HLBM_E_DEVICE, "porosity fill failed"));
   if (launch_init(L, 1.0, nullptr) != hipSuccess) return bail(fail(HLBM_E_DEVICE, "init failed"));
   if (hipStreamSynchronize(L->stream) != hipSuccess) return bail(fail(HLBM_E_DEVICE, "sync failed"));
@@ -350,10 +350,11 @@ hlbm_status hlbm_set_porosity(hlbm_lattice L, const double* d, int64_t n, int32_
 }
 
 hlbm_status hlbm_build_cylinder(hlbm_lattice L, double xc, double yc, double D, const double* noise, int64_t n,
-                                int32_t mem, int32_t noise_mode, double box_half) {
+                                int32_t mem, int32_t noise_mode, double box_half, double d_solid) {
   CHECK_LAT(L);
   if (!std::isfinite(xc) || !std::isfinite(yc) || !(D > 0.0) || !std::isfinite(D))
     return fail(HLBM_E_INVALID, "bad cylinder parameters");
+  if (!(d_solid >= 0.0 && d_solid < 1.0)) return fail(HLBM_E_INVALID, "d_solid must be in [0, 1)");
   if (noise_mode < HLBM_NOISE_NONE || noise_mode > HLBM_NOISE_BOX) return fail(HLBM_E_INVALID, "bad noise mode");
   if (noise && n != L->n) return fail(HLBM_E_INVALID, "noise needs %lld values", (long long)L->n);
   double* dev = nullptr;
@@ -362,7 +363,7 @@ hlbm_status hlbm_build_cylinder(hlbm_lattice L, double xc, double yc, double D, 
     hlbm_status s = staging(L, noise, n, mem, &dev, &owned);
     if (s != HLBM_OK) return s;
   }
-  hipError_t e = launch_cylinder(L, xc, yc, D, dev, noise ? noise_mode : 0, box_half);
+  hipError_t e = launch_cylinder(L, xc, yc, D, dev, noise ? noise_mode : 0, box_half, d_solid);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (owned) dev_free(dev);
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "build_cylinder: %s", hipGetErrorString(e));

@@ -111,7 +111,7 @@ dim3 cell_grid(const hlbm_lattice_s* L);
 // launchers (return hipError_t of the launch)
 hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev);
 hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
-                           const double* noise_dev, int mode, double box_half);
+                           const double* noise_dev, int mode, double box_half, double d_solid);
 hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev);
 hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);

@@ -34,13 +34,23 @@ namespace hlbm {
 // nontemporal variants measured up to 20% slower on lattices whose planes
 // stay resident in the 256 MB Infinity Cache and gave at most a few percent
 // on HBM-resident ones.
+#ifndef HLBM_NT_LOADS
+#define HLBM_NT_LOADS 0
+#endif
+#ifndef HLBM_NT_STORES
+#define HLBM_NT_STORES 0
+#endif
 template <typename S>
 __device__ __forceinline__ S ld_stream(const S* p) {
+  if (HLBM_NT_LOADS) return __builtin_nontemporal_load(p);
   return *p;
 }
 template <typename S>
 __device__ __forceinline__ void st_stream(S* p, S v) {
-  *p = v;
+  if (HLBM_NT_STORES)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Cells whose every neighbour is an ordinary lattice cell: no wall, inlet,
@@ -465,7 +475,7 @@ __global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __res
 template <typename Dd>
 __global__ __launch_bounds__(256) void k_cylinder(const Geo g, Dd* __restrict__ dpor, double xc,
                                                   double yc, double D, const double* __restrict__ noise,
-                                                  int mode, double box_half) {
+                                                  int mode, double box_half, double d_solid) {
   CELL_PROLOGUE
   if (!valid) return;
   const double R = 0.5 * D;
@@ -484,6 +494,8 @@ __global__ __launch_bounds__(256) void k_cylinder(const Geo g, Dd* __restrict__ 
   } else if (noise != nullptr && mode == 2 && fabs(dx) <= box_half && fabs(dy) <= box_half) {
     d = 1.0 - fmin(1.0, fmax(0.0, chi + noise[cell]));
   }
+  // permeable cylinder: the porosity deficit scales with 1 - d_solid
+  if (d_solid != 0.0) d = 1.0 - (1.0 - d) * (1.0 - d_solid);
   dpor[cell] = (Dd)d;
 }
 

@@ -134,13 +134,13 @@ hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev) {
 }
 
 hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
-                           const double* noise_dev, int mode, double box_half) {
+                           const double* noise_dev, int mode, double box_half, double d_solid) {
   if (L->desc.precision == HLBM_FP64)
     k_cylinder<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, xc, yc,
-                                                               D, noise_dev, mode, box_half);
+                                                               D, noise_dev, mode, box_half, d_solid);
   else
     k_cylinder<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, xc, yc, D,
-                                                              noise_dev, mode, box_half);
+                                                              noise_dev, mode, box_half, d_solid);
   return hipGetLastError();
 }
 

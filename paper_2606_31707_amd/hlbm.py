@@ -116,7 +116,7 @@ def load_library(path: str = LIB_PATH):
         "hlbm_destroy": (None, [vp]),
         "hlbm_footprint_bytes": (i32, [P(Desc), i32, i32, P(C.c_uint64)]),
         "hlbm_set_porosity": (i32, [vp, vp, i64, i32]),
-        "hlbm_build_cylinder": (i32, [vp, dbl, dbl, dbl, vp, i64, i32, i32, dbl]),
+        "hlbm_build_cylinder": (i32, [vp, dbl, dbl, dbl, vp, i64, i32, i32, dbl, dbl]),
         "hlbm_init_equilibrium": (i32, [vp, dbl, vp, i64, i32]),
         "hlbm_set_populations": (i32, [vp, vp, i64, i32]),
         "hlbm_get_populations": (i32, [vp, vp, i64, i32]),
@@ -239,10 +239,10 @@ class Lattice:
         p, n, mem, _keep = _arr_in(d, self.n)
         _check(self._lib.hlbm_set_porosity(self._h, p, n, mem))
 
-    def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0):
+    def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0, d_solid=0.0):
         p, n, mem, _keep = _arr_in(noise, self.n)
         _check(self._lib.hlbm_build_cylinder(self._h, xc, yc, D, p, n if noise is not None else 0,
-                                             mem, noise_mode, box_half))
+                                             mem, noise_mode, box_half, d_solid))
 
     def init_equilibrium(self, rho0=1.0, u=None):
         p, n, mem, _keep = _arr_in(u, 3 * self.n)

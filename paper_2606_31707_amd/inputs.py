@@ -15,6 +15,14 @@ Workload recipes (stand-ins for the paper's cylinder cases, Sec. 5):
   autograd_re40  2D 400 x 160, D = 40 at (160, 79.5), u_max = 0.03, Re = 40,
                  solid-fraction noise U[0, 0.05] in |x-x_c|, |y-y_c| <= 2D
                  (seeds 400..431), drag plane x = 360.
+  porous3d_re40  the steady 3D validation case of Sec. 5.2 in lattice units:
+                 3.6 x 0.8 x 0.4 m at N = 21 cells per diameter (dx = 0.1/21 m)
+                 -> 756 x 168 x 84 D3Q19, D = 21 at (251.5, 83.5), tau = 0.55,
+                 uniform inflow at Re = 40, y and z periodic, permeable
+                 cylinder K = 1e-6 m^2 (core porosity 1 - tau nu / K in
+                 lattice units = 0.792), drag plane x = 357 (1.7 m),
+                 dissipation box x in [21, 482] (1.2 +- 1.1 m); T = 32 s =
+                 42 336 steps.
 """
 from __future__ import annotations
 
@@ -54,6 +62,7 @@ class Workload:
     box_half: float = 0.0
     velocity_noise: float = 0.0   # amplitude of the initial velocity noise
     primal_steps: int = 4000
+    d_solid: float = 0.0          # porosity inside a permeable cylinder
     extra: dict = field(default_factory=dict)
 
     @property
@@ -103,6 +112,18 @@ def autograd_re40(seed: int = 400) -> Workload:
     return Workload(f"autograd_re40_400x160_s{seed}", D2Q9, 400, 160, 1, 0.03, INLET_PARABOLIC, 40.0,
                     40.0, 160.0, 79.5, objective=OBJ_FFA, lo=(360, 0, 0), hi=(360, 159, 0),
                     noise_mode=NOISE_BOX, noise_amp=0.05, noise_seed=seed, box_half=80.0)
+
+
+def porous3d_re40() -> Workload:
+    dx = 0.1 / 21.0                       # m per cell (N = 21 over D = 0.1 m)
+    tau = 0.55
+    nu_l = (tau - 0.5) / 3.0
+    k_l = 1e-6 / (dx * dx)                # permeability in lattice units
+    u = 40.0 * nu_l / 21.0                # Re = u D / nu
+    return Workload("porous3d_re40_756x168x84", D3Q19, 756, 168, 84, u, INLET_UNIFORM, 40.0, 21.0, 251.5,
+                    83.5, bc_y=BC_PERIODIC, bc_z=BC_PERIODIC, objective=OBJ_FFA, lo=(357, 0, 0),
+                    hi=(357, 167, 83), primal_steps=42336, d_solid=1.0 - tau * nu_l / k_l,
+                    extra={"dissipation_box": ((21, 0, 0), (482, 167, 83))})
 
 
 def scaled(w: Workload, factor: float, name: str | None = None) -> Workload:

@@ -115,6 +115,28 @@ def test_cylinder_with_noise(mode):
     compare_state(s, L, G)
 
 
+@pytest.mark.parametrize("stencil", [O.D2Q9, O.D3Q19])
+def test_permeable_cylinder(stencil):
+    """Permeable cylinder (core porosity d_solid, the validation cases' K):
+    the porosity field and 200 steps on both sides."""
+    w = I.scaled(I.porous3d_re40(), 1.0 / 6.0)
+    nz = w.nz if stencil == O.D3Q19 else 1
+    s = Spec(stencil=stencil, nx=w.nx, ny=w.ny, nz=nz, tau=0.6, u_in=0.04, bc_y=O.BC_PERIODIC,
+             inlet_profile=O.INLET_UNIFORM, cyl=(w.xc, w.yc, w.D))
+    say("permeable cylinder", stencil)
+    L = make_oracle(s)
+    L.build_cylinder(w.xc, w.yc, w.D, d_solid=w.d_solid)
+    L.init_equilibrium(1.0, None)
+    G = make_gpu(s)
+    G.build_cylinder(w.xc, w.yc, w.D, d_solid=w.d_solid)
+    G.init_equilibrium(1.0, None)
+    assert rel_err(G.porosity(), L.porosity()) < 1e-15
+    assert abs(G.porosity().min() - w.d_solid) < 1e-15
+    L.step(200)
+    G.run_primal(200)
+    compare_state(s, L, G)
+
+
 @pytest.mark.parametrize("kind", [O.OBJ_FFA, O.OBJ_DISS, O.OBJ_MOMENTUM])
 def test_window_means_and_objective(kind):
     s = channel(obj=None, tau=0.56, u_in=0.05)

@@ -292,3 +292,38 @@ def test_objective_region_rejects_inlet_column():
     L = _channel()
     with pytest.raises(ValueError):
         L.set_objective(O.OBJ_FFA, (0, 0, 0), (0, 11, 0))
+
+
+@pytest.mark.parametrize("obj,bcz", [(O.OBJ_FFA, O.BC_PERIODIC), (O.OBJ_DISS, O.BC_WALLS)])
+def test_steady_gradient_d3q19_matches_finite_differences(obj, bcz):
+    """The laminar 3D case (D3Q19; periodic or bounce-back z walls): the steady
+    adjoint gradient against central finite differences of the converged J."""
+    L = _channel(O.D3Q19, 5, bc_z=bcz, u_in=0.04, tau=0.7)
+    nx, ny, nz = L.p.nx, L.p.ny, L.p.nz
+    if obj == O.OBJ_FFA:
+        L.set_objective(obj, (16, 0, 0), (16, ny - 1, nz - 1), u0=0.04)
+    else:
+        L.set_objective(obj, (2, 0, 0), (20, ny - 1, nz - 1))
+    d0 = L.porosity()
+    J0 = _solve(L, d0)
+    f0 = L.populations()
+    L.adjoint_prepare(0, 0.0, O.TURB_DIFFERENTIATED)
+    k, res = L.adjoint_solve(200000, 1e-14, 100)
+    assert res < 1e-14
+    g = L.gradient()
+    for (x, y, z) in [(5, 4, 2), (8, 6, 0), (9, 5, 4)]:
+        c = x + nx * (y + ny * z)
+        h = 1e-4
+        assert 2 * h < d0[c] < 1 - 2 * h or d0[c] in (0.0, 1.0)
+        if 2 * h < d0[c] < 1 - 2 * h:
+            dp, dm = d0.copy(), d0.copy()
+            dp[c] += h
+            dm[c] -= h
+            fd = (_solve(L, dp, f0) - _solve(L, dm, f0)) / (2 * h)
+        else:
+            s = -1.0 if d0[c] > 0.5 else 1.0
+            d1, d2 = d0.copy(), d0.copy()
+            d1[c] += s * h
+            d2[c] += 2 * s * h
+            fd = s * (-3 * J0 + 4 * _solve(L, d1, f0) - _solve(L, d2, f0)) / (2 * h)
+        assert abs(g[c] - fd) < 1e-6 * abs(fd), ((x, y, z), g[c], fd)

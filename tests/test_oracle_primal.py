@@ -231,3 +231,20 @@ def test_channel_pressure_outlet_keeps_flow():
     rc = r2.reshape(16, 64)[8, 4:60]
     assert np.all(np.diff(rc) < 0)  # pressure falls along the channel
     assert np.ptp(np.diff(rc)) < 0.1 * abs(np.diff(rc).mean())  # entrance/exit effects only
+
+
+def test_permeable_cylinder_porosity():
+    """d_solid sets the porosity of the cylinder core (Sec. 2.1: d = 1 - dx^2
+    tau nu / K), the ramp scales with 1 - d_solid, d_solid = 0 is the solid
+    cylinder."""
+    p = O.Params(nx=40, ny=30, tau=0.55)
+    A, B = O.Lattice(p), O.Lattice(p)
+    A.build_cylinder(15.0, 14.5, 12.0)
+    B.build_cylinder(15.0, 14.5, 12.0, d_solid=0.792)
+    a, b = A.porosity(), B.porosity()
+    x, y = np.arange(40 * 30) % 40, np.arange(40 * 30) // 40
+    r = np.hypot(x - 15.0, y - 14.5)
+    assert np.all(a[r <= 5.0] == 0.0) and np.all(b[r <= 5.0] == 0.792)
+    assert np.all(b[r >= 7.0] == 1.0) and np.all(a[r >= 7.0] == 1.0)
+    ramp = (r > 5.0) & (r < 7.0)
+    assert np.allclose(1.0 - b[ramp], (1.0 - a[ramp]) * (1.0 - 0.792), rtol=0, atol=1e-15)
