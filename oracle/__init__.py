@@ -20,7 +20,7 @@ from .build import LIB_PATH, build
 D2Q9, D3Q19 = 0, 1
 BC_PERIODIC, BC_WALLS, BC_INLET_OUTLET = 0, 1, 2
 INLET_UNIFORM, INLET_PARABOLIC = 1, 2
-OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM = 0, 1, 2
+OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM, OBJ_MEA = 0, 1, 2, 3
 TURB_FROZEN, TURB_DIFFERENTIATED = 0, 1
 NOISE_NONE, NOISE_RIM, NOISE_BOX = 0, 1, 2
 
@@ -72,6 +72,8 @@ def _load():
         "orc_moments": (C.c_int, [vp, _DP, _DP]),
         "orc_set_objective": (C.c_int, [vp, C.c_int, _IP, _IP, C.c_double, C.c_double]),
         "orc_objective": (C.c_double, [vp]),
+        "orc_mea_surface": (C.c_int, [vp, vp]),
+        "orc_mea_source": (C.c_int, [vp, _DP]),
         "orc_window_reset": (None, [vp]),
         "orc_window_sample": (None, [vp]),
         "orc_window_count": (C.c_long, [vp]),
@@ -293,6 +295,20 @@ class Lattice:
 
     def objective(self) -> float:
         return self._lib.orc_objective(self._h)
+
+    def mea_surface(self) -> np.ndarray:
+        """Surface flags of J_MEA (set_objective(OBJ_MEA, ...) first)."""
+        out = np.zeros(self.n, np.uint8)
+        if self._lib.orc_mea_surface(self._h, out.ctypes.data_as(C.c_void_p)) != 0:
+            raise ValueError("no objective set")
+        return out
+
+    def mea_source(self) -> np.ndarray:
+        """dJ_MEA/df as [q, n]."""
+        out = np.zeros(self.q * self.n)
+        if self._lib.orc_mea_source(self._h, out) != 0:
+            raise ValueError("objective is not MEA")
+        return out.reshape(self.q, self.n)
 
     def window_reset(self):
         self._lib.orc_window_reset(self._h)

@@ -770,7 +770,8 @@ static int in_region(const orc_lattice* L, long c) {
 int orc_set_objective(orc_lattice* L, int kind, const int* lo, const int* hi, double u0,
                       double p0) {
   int n3[3] = {L->p.nx, L->p.ny, L->p.nz};
-  if (kind < ORC_OBJ_FFA || kind > ORC_OBJ_MOMENTUM) return -1;
+  if (kind < ORC_OBJ_FFA || kind > ORC_OBJ_MEA) return -1;
+  if (kind == ORC_OBJ_MEA && !(u0 > 0.0)) return -1; /* u0 = surface area A */
   for (int a = 0; a < 3; ++a) {
     if (lo[a] < 0 || hi[a] >= n3[a] || lo[a] > hi[a]) return -1;
   }
@@ -787,7 +788,100 @@ int orc_set_objective(orc_lattice* L, int kind, const int* lo, const int* hi, do
   return 0;
 }
 
+/* Lattice neighbour x + xi_i (periodic axes wrap), or -1 when that position
+ * is not a lattice cell (across a wall, beyond either x end). */
+static long lattice_neighbour(const orc_lattice* L, long c, int i) {
+  int n3[3] = {L->p.nx, L->p.ny, L->p.nz};
+  int bc[3] = {L->p.bc_x, L->p.bc_y, L->p.bc_z};
+  int x[3];
+  cell_coords(L, c, &x[0], &x[1], &x[2]);
+  for (int a = 0; a < 3; ++a) {
+    x[a] += L->c[i][a];
+    if (x[a] < 0 || x[a] >= n3[a]) {
+      if (bc[a] != ORC_BC_PERIODIC) return -1;
+      x[a] = (x[a] + n3[a]) % n3[a];
+    }
+  }
+  return cell_index(L, x[0], x[1], x[2]);
+}
+
+/* Surface node set of J_MEA (Sec. 4): the cylinder's boundary nodes, read
+ * for a porosity field as cells with d < 1/2 that have a lattice neighbour
+ * with d >= 1/2, taken inside the objective box and one cell away from its
+ * faces (on axes the box does not span completely), so that every
+ * neighbour the functional reads lies in the box as well. */
+static int mea_surface(const orc_lattice* L, long c) {
+  int n3[3] = {L->p.nx, L->p.ny, L->p.nz};
+  int x[3];
+  cell_coords(L, c, &x[0], &x[1], &x[2]);
+  for (int a = 0; a < 3; ++a) {
+    int lo = L->lo[a], hi = L->hi[a];
+    if (!(lo == 0 && hi == n3[a] - 1)) {
+      lo += 1;
+      hi -= 1;
+    }
+    if (x[a] < lo || x[a] > hi) return 0;
+  }
+  if (L->d[c] >= 0.5) return 0;
+  for (int i = 1; i < L->q; ++i) {
+    long nb = lattice_neighbour(L, c, i);
+    if (nb >= 0 && L->d[nb] >= 0.5) return 1;
+  }
+  return 0;
+}
+
+/* J_MEA = (1/A) sum_{x in surface} sum_i xi_i,x (f_i(x + xi_i) - f_opp(i)(x)),
+ * the x component (n = e_x) of the momentum exchanged across the surface
+ * (Sec. 4, Eq. obj_mea), on the post-stream state; a neighbour that is not
+ * a lattice cell contributes nothing. */
+static double mea_objective(const orc_lattice* L) {
+  int q = L->q;
+  double J = 0.0;
+  for (long c = 0; c < L->n; ++c) {
+    if (!mea_surface(L, c)) continue;
+    for (int i = 0; i < q; ++i) {
+      long nb = lattice_neighbour(L, c, i);
+      double fi = (nb >= 0) ? L->f[nb * q + i] : 0.0;
+      J += L->c[i][0] * (fi - L->f[c * q + L->opp[i]]);
+    }
+  }
+  return J / L->u0;
+}
+
+/* dJ_MEA/df: J is linear in f; every term xi_i,x f_i(x + xi_i) / A and
+ * -xi_i,x f_opp(i)(x) / A adds its coefficient to the slot it reads.
+ * g is slot-major [c*q + i]. */
+static void mea_source_slots(const orc_lattice* L, double* g) {
+  int q = L->q;
+  memset(g, 0, sizeof(double) * L->n * q);
+  for (long c = 0; c < L->n; ++c) {
+    if (!mea_surface(L, c)) continue;
+    for (int i = 0; i < q; ++i) {
+      long nb = lattice_neighbour(L, c, i);
+      if (nb >= 0) g[nb * q + i] += L->c[i][0] / L->u0;
+      g[c * q + L->opp[i]] -= L->c[i][0] / L->u0;
+    }
+  }
+}
+
+int orc_mea_surface(const orc_lattice* L, unsigned char* flags) {
+  if (!L->obj_set) return -1;
+  for (long c = 0; c < L->n; ++c) flags[c] = (unsigned char)mea_surface(L, c);
+  return 0;
+}
+
+int orc_mea_source(const orc_lattice* L, double* g) {
+  if (!L->obj_set || L->obj_kind != ORC_OBJ_MEA) return -1;
+  double* t = (double*)malloc(sizeof(double) * L->n * L->q);
+  mea_source_slots(L, t);
+  for (long c = 0; c < L->n; ++c)
+    for (int i = 0; i < L->q; ++i) g[(long)i * L->n + c] = t[c * L->q + i];
+  free(t);
+  return 0;
+}
+
 double orc_objective(const orc_lattice* L) {
+  if (L->obj_kind == ORC_OBJ_MEA) return mea_objective(L);
   stencil_t s = lat_stencil(L);
   double J = 0.0;
   for (long c = 0; c < L->n; ++c)
@@ -811,11 +905,18 @@ void orc_window_sample(orc_lattice* L) {
   stencil_t s = lat_stencil(L);
   int q = s.q;
   double g[QMAX];
+  const int mea = L->obj_set && L->obj_kind == ORC_OBJ_MEA;
+  if (mea) { /* dJ_MEA/df is constant; dJ_MEA/dd = 0 */
+    double* t = (double*)malloc(sizeof(double) * L->n * q);
+    mea_source_slots(L, t);
+    for (long k = 0; k < L->n * q; ++k) L->gsum[k] += t[k];
+    free(t);
+  }
   for (long c = 0; c < L->n; ++c) {
     const double* fc = L->f + c * q;
     for (int i = 0; i < q; ++i) L->fsum[c * q + i] += fc[i];
     L->tau_sum[c] += tau_eff_s(&s, fc, L->p.tau, L->p.cs);
-    if (L->obj_set && in_region(L, c)) {
+    if (L->obj_set && !mea && in_region(L, c)) {
       dJdf_s(&s, L->obj_kind, fc, L->d[c], L->p.tau, L->u0, L->p0, g);
       for (int i = 0; i < q; ++i) L->gsum[c * q + i] += g[i];
       L->dJdd_sum[c] += dJdd_s(&s, L->obj_kind, fc, L->d[c], L->p.tau);
@@ -863,6 +964,15 @@ int orc_adjoint_prepare(orc_lattice* L, int source, double tau_adj, int turb) {
     L->lam = (double*)calloc(nq, sizeof(double));
   }
   double inv = (source == 1) ? 1.0 / (double)L->nsamp : 1.0;
+  const int mea = L->obj_kind == ORC_OBJ_MEA;
+  double* gmea = NULL;
+  if (mea) {
+    gmea = (double*)malloc(sizeof(double) * nq);
+    if (source == 1)
+      for (long k = 0; k < nq; ++k) gmea[k] = L->gsum[k] * inv;
+    else
+      mea_source_slots(L, gmea);
+  }
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < L->n; ++c) {
     double fs[QMAX];
@@ -890,7 +1000,10 @@ int orc_adjoint_prepare(orc_lattice* L, int source, double tau_adj, int turb) {
     else
       tau_used = tau_frozen;
     dcdd_s(&s, fs, L->d[c], tau_used, L->dcdd + c * q);
-    if (in_region(L, c)) {
+    if (mea) { /* a source on the surface cells and their neighbours */
+      for (int i = 0; i < q; ++i) L->gsrc[c * q + i] = gmea[c * q + i];
+      L->dJdd[c] = 0.0;
+    } else if (in_region(L, c)) {
       if (source == 1) {
         for (int i = 0; i < q; ++i) L->gsrc[c * q + i] = L->gsum[c * q + i] * inv;
         L->dJdd[c] = L->dJdd_sum[c] * inv;
@@ -903,6 +1016,7 @@ int orc_adjoint_prepare(orc_lattice* L, int source, double tau_adj, int turb) {
       L->dJdd[c] = 0.0;
     }
   }
+  free(gmea);
   L->adj_ready = 1;
   orc_adjoint_reset(L);
   return 0;

@@ -34,7 +34,7 @@ extern "C" {
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_WALLS = 1, ORC_BC_INLET_OUTLET = 2 };
 enum { ORC_INLET_UNIFORM = 1, ORC_INLET_PARABOLIC = 2 };
-enum { ORC_OBJ_FFA = 0, ORC_OBJ_DISS = 1, ORC_OBJ_MOMENTUM = 2 };
+enum { ORC_OBJ_FFA = 0, ORC_OBJ_DISS = 1, ORC_OBJ_MOMENTUM = 2, ORC_OBJ_MEA = 3 };
 enum { ORC_TURB_FROZEN = 0, ORC_TURB_DIFFERENTIATED = 1 };
 enum { ORC_NOISE_NONE = 0, ORC_NOISE_RIM = 1, ORC_NOISE_BOX = 2 };
 
@@ -81,10 +81,17 @@ int orc_step(orc_lattice* L, long nsteps);
 long orc_run_steady(orc_lattice* L, long max_steps, double tol, long check_every);
 int orc_moments(const orc_lattice* L, double* rho, double* u /* 3*n */);
 
-/* Objective region: inclusive box lo..hi. */
+/* Objective region: inclusive box lo..hi.  For ORC_OBJ_MEA (drag by the
+ * momentum exchange algorithm, Sec. 4 Eq. obj_mea) u0 carries the surface
+ * area A (the perimeter in 2D) and the surface set is the box cells (away
+ * from the box faces on axes the box does not span completely) with d < 1/2
+ * and a lattice neighbour with d >= 1/2. */
 int orc_set_objective(orc_lattice* L, int kind, const int* lo, const int* hi,
                       double u0, double p0);
 double orc_objective(const orc_lattice* L);
+/* J_MEA surface flags (1 on surface cells) and dJ_MEA/df ([i*n + c]). */
+int orc_mea_surface(const orc_lattice* L, unsigned char* flags);
+int orc_mea_source(const orc_lattice* L, double* g);
 
 /* Tracking average (window) of the post-stream state. */
 void orc_window_reset(orc_lattice* L);
