@@ -82,8 +82,10 @@ typedef enum { HLBM_INLET_UNIFORM = 1, HLBM_INLET_PARABOLIC = 2 } hlbm_inlet;
 /* Objectives (Sec. 4).  FFA: far-field drag over a plane, Eq. obj_ffa, with
  * p = rho/3.  DISS: viscous + porous dissipation over a box, Eq. obj_diss,
  * S = -Pi/(2 tau0 c_s^2) from the non-equilibrium part with respect to
- * f^eq(rho, u), nu/K = (1 - d)/tau0.  MOMENTUM: sum of j_x (test objective). */
-typedef enum { HLBM_OBJ_FFA = 0, HLBM_OBJ_DISS = 1, HLBM_OBJ_MOMENTUM = 2 } hlbm_objective;
+ * f^eq(rho, u), nu/K = (1 - d)/tau0.  MOMENTUM: sum of j_x (test objective).
+ * MEA: drag by momentum exchange on the cylinder's surface nodes, Eq.
+ * obj_mea (see hlbm_set_objective). */
+typedef enum { HLBM_OBJ_FFA = 0, HLBM_OBJ_DISS = 1, HLBM_OBJ_MOMENTUM = 2, HLBM_OBJ_MEA = 3 } hlbm_objective;
 
 /* Treatment of the Smagorinsky closure in the adjoint (Sec. 5.4).  FROZEN:
  * frozen-turbulence assumption, relaxation time tau_adj + (mean tau_eff -
@@ -188,7 +190,14 @@ hlbm_status hlbm_get_populations(hlbm_lattice lat, double* f, int64_t n_values, 
 
 /* Objective over the inclusive box lo..hi (a one-cell-thick plane for FFA).
  * With INLET_OUTLET the box may not touch column 0.  u0, p0: FFA reference
- * velocity and pressure (p0 = 1/3 for rho = 1). */
+ * velocity and pressure (p0 = 1/3 for rho = 1).
+ * HLBM_OBJ_MEA (Sec. 4 Eq. obj_mea, drag by momentum exchange on the
+ * surface nodes, n = e_x): u0 carries the surface area A (the perimeter in
+ * 2D; must be > 0), p0 is unused.  The surface nodes are the box cells with
+ * d < 1/2 and a lattice neighbour with d >= 1/2, kept one cell away from the
+ * box faces on axes the box does not span completely; they follow later
+ * porosity changes.  J_MEA is linear in f: its adjoint source is constant
+ * and dJ/dd = 0 (the surface set is piecewise constant in d). */
 hlbm_status hlbm_set_objective(hlbm_lattice lat, int32_t kind, const int32_t lo[3],
                                const int32_t hi[3], double u0, double p0);
 

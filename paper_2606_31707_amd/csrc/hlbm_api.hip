@@ -132,6 +132,15 @@ hlbm_status finish_out(hlbm_lattice_s* L, double* dev, double* out, int64_t coun
   return HLBM_OK;
 }
 
+// J_MEA reads its surface flags; they follow the porosity and the region.
+hlbm_status ensure_mea(hlbm_lattice_s* L) {
+  if (!L->obj_set || L->obj_kind != HLBM_OBJ_MEA || !L->mea_dirty) return HLBM_OK;
+  hipError_t e = launch_mea_flags(L);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "J_MEA surface flags: %s", hipGetErrorString(e));
+  L->mea_dirty = 0;
+  return HLBM_OK;
+}
+
 hlbm_status ensure_window(hlbm_lattice_s* L) {
   const int64_t P = L->plane;
   hlbm_status s;
@@ -306,7 +315,7 @@ void hlbm_destroy(hlbm_lattice L) {
   (void)hipStreamSynchronize(L->stream);
   void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
-                  L->red, L->usnap, L->probe_buf};
+                  L->red, L->usnap, L->probe_buf, L->mea_flag};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
   if (L->ev0) (void)hipEventDestroy(L->ev0);
@@ -346,6 +355,7 @@ hlbm_status hlbm_set_porosity(hlbm_lattice L, const double* d, int64_t n, int32_
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "set_porosity: %s", hipGetErrorString(e));
   if (hbad) return fail(HLBM_E_INVALID, "porosity outside [0, 1] or not finite");
   L->adj_ready = 0;
+  L->mea_dirty = 1;
   return HLBM_OK;
 }
 
@@ -368,6 +378,7 @@ hlbm_status hlbm_build_cylinder(hlbm_lattice L, double xc, double yc, double D, 
   if (owned) dev_free(dev);
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "build_cylinder: %s", hipGetErrorString(e));
   L->adj_ready = 0;
+  L->mea_dirty = 1;
   return HLBM_OK;
 }
 
@@ -427,7 +438,8 @@ hlbm_status hlbm_get_populations(hlbm_lattice L, double* f, int64_t n_values, in
 hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3], const int32_t hi[3], double u0,
                                double p0) {
   CHECK_LAT(L);
-  if (kind < HLBM_OBJ_FFA || kind > HLBM_OBJ_MOMENTUM) return fail(HLBM_E_INVALID, "bad objective kind");
+  if (kind < HLBM_OBJ_FFA || kind > HLBM_OBJ_MEA) return fail(HLBM_E_INVALID, "bad objective kind");
+  if (kind == HLBM_OBJ_MEA && !(u0 > 0.0)) return fail(HLBM_E_INVALID, "J_MEA needs the surface area A > 0 in u0");
   if (!lo || !hi) return fail(HLBM_E_INVALID, "null region");
   const int nn[3] = {L->desc.nx, L->desc.ny, L->desc.nz};
   for (int a = 0; a < 3; ++a)
@@ -441,12 +453,17 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
   if (rp > L->rplane) {
     dev_free(L->acc_obj);
     dev_free(L->src);
+    dev_free(L->mea_flag);
     L->acc_obj = nullptr;
     L->src = nullptr;
+    L->mea_flag = nullptr;
+    L->rplane = 0;
   }
   hlbm_status s;
   if ((s = dev_alloc((void**)&L->acc_obj, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
   if ((s = dev_alloc((void**)&L->src, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
+  if (kind == HLBM_OBJ_MEA && (s = dev_alloc((void**)&L->mea_flag, rp)) != HLBM_OK) return s;
+  L->mea_dirty = 1;
   L->rplane = rp > L->rplane ? rp : L->rplane;
   L->obj_kind = kind;
   for (int a = 0; a < 3; ++a) {
@@ -545,6 +562,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
   if (!(steady_tol >= 0.0)) return fail(HLBM_E_INVALID, "steady_tol must be >= 0");
   if (check_every <= 0) check_every = 100;
   hlbm_status s;
+  if ((s = ensure_mea(L)) != HLBM_OK) return s;
   if (accumulate) {
     if ((s = ensure_window(L)) != HLBM_OK) return s;
   }
@@ -603,6 +621,8 @@ hlbm_status hlbm_get_objective(hlbm_lattice L, int32_t which, double* J) {
   if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
   if (which == 1 && L->nsamp == 0) return fail(HLBM_E_STATE, "empty window");
   if (which != 0 && which != 1) return fail(HLBM_E_INVALID, "which must be 0 or 1");
+  hlbm_status s = ensure_mea(L);
+  if (s != HLBM_OK) return s;
   int nbl = 0;
   HIP_TRY(launch_objective(L, which, L->red, &nbl));
   return reduce_to_host(L, nbl, 0, J);
@@ -621,6 +641,10 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
   const double tau_adj = o->tau_adj > 0.0 ? o->tau_adj : L->desc.tau;
   if (!(tau_adj > 0.5)) return fail(HLBM_E_INVALID, "tau_adj must exceed 1/2");
   if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
+  {
+    hlbm_status s0 = ensure_mea(L);
+    if (s0 != HLBM_OK) return s0;
+  }
   const bool smag = L->desc.smagorinsky_cs > 0.0;
   if (o->source == HLBM_SOURCE_MEAN) {
     if (L->nsamp == 0 || !L->acc_rho) return fail(HLBM_E_STATE, "mean-flow adjoint needs a non-empty window");
@@ -862,6 +886,7 @@ extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, co
   HIP_TRY(hipStreamSynchronize(g->stream));
   hlbm_status s;
   for (int i = 0; i < count; ++i) {
+    if ((s = ensure_mea(lats[i])) != HLBM_OK) return s;
     if (modes[i] == HLBM_GROUP_PRIMAL_WINDOW && (s = ensure_window(lats[i])) != HLBM_OK) return s;
     HIP_TRY(hipStreamSynchronize(lats[i]->stream));
   }

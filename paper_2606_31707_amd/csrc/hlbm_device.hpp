@@ -13,7 +13,7 @@
 namespace hlbm {
 
 enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_INOUT = 2 };
-enum { OBJ_FFA = 0, OBJ_DISS = 1, OBJ_MOMENTUM = 2 };
+enum { OBJ_FFA = 0, OBJ_DISS = 1, OBJ_MOMENTUM = 2, OBJ_MEA = 3 };
 enum { NB_CELL = 0, NB_BOUNCE = 1, NB_OUTLET = 2, NB_DROP = 3 };
 
 #ifndef HLBM_TILE_BX

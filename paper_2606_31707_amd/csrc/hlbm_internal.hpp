@@ -38,6 +38,8 @@ struct hlbm_lattice_s {
   int lo[3] = {0, 0, 0}, rn[3] = {1, 1, 1};
   int64_t rplane = 0;
   double u0 = 0.0, p0 = 1.0 / 3.0;
+  unsigned char* mea_flag = nullptr;  // rplane: J_MEA surface nodes of the region
+  int mea_dirty = 1;                  // flags to rebuild (porosity or region changed)
 
   // adjoint
   void* phi = nullptr;    // q * plane (double for FP64, float otherwise)
@@ -92,7 +94,8 @@ struct ObjBox {
   int active, kind;
   int lo[3], rn[3];
   int64_t rplane;
-  double u0, p0, tau0;
+  double u0, p0, tau0;           // J_MEA: u0 carries the surface area A
+  const unsigned char* flag;     // J_MEA surface nodes over the region (else null)
 };
 
 struct Acc {
@@ -113,6 +116,7 @@ hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev);
 hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
                            const double* noise_dev, int mode, double box_half, double d_solid);
 hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev);
+hipError_t launch_mea_flags(hlbm_lattice_s* L);
 hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);
 hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev);

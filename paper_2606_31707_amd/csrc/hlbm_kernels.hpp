@@ -204,6 +204,37 @@ __device__ __forceinline__ bool region_index(const ObjBox& ob, int x, int y, int
   return true;
 }
 
+// ---- J_MEA, the momentum-exchange drag (Sec. 4, Eq. obj_mea) -------------
+// J = (1/A) sum_{x in surface} sum_i xi_i,x (f_i(x + xi_i) - f_opp(i)(x)) is
+// linear in f.  Collected by the slot each term reads it is
+// J = sum_y sum_k g_k(y) f_k(y),  g_k(y) = (xi_k,x / A)(s(y) + s(y - xi_k)),
+// with s the surface flag (0 unless y - xi_k is a lattice cell of the
+// region).  g is the constant adjoint source; dJ/dd = 0.
+template <int Q>
+__device__ __forceinline__ double mea_g(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
+                                        int k) {
+  using L = Lat<Q>;
+  if (L::cx[k] == 0) return 0.0;
+  double s = (double)ob.flag[r];
+  int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+  int64_t rr;
+  if (classify(g, sx, sy, sz) == NB_CELL && region_index<Q>(ob, sx, sy, sz, rr)) s += (double)ob.flag[rr];
+  return (double)L::cx[k] / ob.u0 * s;
+}
+
+// Region-cell terms of J_MEA from the shifted state sd (only J is nonzero).
+template <int Q>
+__device__ void mea_terms(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
+                          const double (&sd)[Q], double* out) {
+  using L = Lat<Q>;
+#pragma unroll
+  for (int m = 0; m < Coef<Q>::N; ++m) out[m] = 0.0;
+  double J = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) J += mea_g<Q>(g, ob, x, y, z, r, k) * (sd[k] + L::w[k]);
+  out[Coef<Q>::J] = J;
+}
+
 // AA odd-step pull of direction k into cell (x, y, z): post-collision value of
 // the upstream cell (stored swapped), bounce-back from the own cell, or the
 // outlet's virtual column.
@@ -352,11 +383,15 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       double sd[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
-      double dr, ax, ay, az, P[6];
-      cell_moments<Q, double>(sd, dr, ax, ay, az);
-      neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
       double terms[Coef<Q>::N];
-      objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
+      if (ob.kind == OBJ_MEA) {
+        mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
+      } else {
+        double dr, ax, ay, az, P[6];
+        cell_moments<Q, double>(sd, dr, ax, ay, az);
+        neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
+        objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
+      }
 #pragma unroll
       for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
     }
@@ -497,6 +532,34 @@ __global__ __launch_bounds__(256) void k_cylinder(const Geo g, Dd* __restrict__ 
   // permeable cylinder: the porosity deficit scales with 1 - d_solid
   if (d_solid != 0.0) d = 1.0 - (1.0 - d) * (1.0 - d_solid);
   dpor[cell] = (Dd)d;
+}
+
+// J_MEA surface nodes of the objective region: d < 1/2 with a lattice
+// neighbour d >= 1/2, one cell away from the region's faces on axes the
+// region does not span completely (the functional reads every neighbour of
+// a surface node, which must lie in the region as well).
+template <int Q, typename Dd>
+__global__ __launch_bounds__(256) void k_mea_flags(const Geo g, const ObjBox ob, const Dd* __restrict__ dpor,
+                                                   unsigned char* __restrict__ flag) {
+  using L = Lat<Q>;
+  CELL_PROLOGUE
+  if (!valid) return;
+  int64_t r;
+  if (!region_index<Q>(ob, x, y, z, r)) return;
+  const int n3[3] = {g.nx, g.ny, g.nz}, p[3] = {x, y, z};
+  bool inner = true;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = ob.lo[a], hi = ob.lo[a] + ob.rn[a] - 1;
+    if (!(lo == 0 && hi == n3[a] - 1) && (p[a] <= lo || p[a] >= hi)) inner = false;
+  }
+  unsigned char s = 0;
+  if (inner && (double)dpor[cell] < 0.5) {
+    for (int k = 1; k < Q; ++k) {
+      int tx = x + L::cx[k], ty = y + L::cy[k], tz = z + L::cz[k];
+      if (classify(g, tx, ty, tz) == NB_CELL && (double)dpor[cell_of(g, tx, ty, tz)] >= 0.5) s = 1;
+    }
+  }
+  flag[r] = s;
 }
 
 template <typename Dd>
@@ -677,11 +740,15 @@ __global__ __launch_bounds__(256) void k_objective(const Geo g, const ObjBox ob,
       double sd[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
-      double dr, jx, jy, jz, P[6];
-      cell_moments<Q, double>(sd, dr, jx, jy, jz);
-      neq_flux<Q, double>(sd, dr, jx, jy, jz, 1.0 / (1.0 + dr), P);
       double terms[Coef<Q>::N];
-      objective_terms<Q>(ob, (double)dpor[cell], dr, jx, jy, jz, P, terms);
+      if (ob.kind == OBJ_MEA) {
+        mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
+      } else {
+        double dr, jx, jy, jz, P[6];
+        cell_moments<Q, double>(sd, dr, jx, jy, jz);
+        neq_flux<Q, double>(sd, dr, jx, jy, jz, 1.0 / (1.0 + dr), P);
+        objective_terms<Q>(ob, (double)dpor[cell], dr, jx, jy, jz, P, terms);
+      }
       v = terms[Coef<Q>::J];
     }
   }
@@ -831,10 +898,14 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
 #pragma unroll
       for (int m = 0; m < Coef<Q>::N; ++m) src[m * ob.rplane + r] = pin.acc_obj[m * ob.rplane + r] * pin.inv;
     } else {
-      double Pq[6];
-      neq_flux<Q, double>(fs, drho, jx, jy, jz, ir, Pq);
       double terms[Coef<Q>::N];
-      objective_terms<Q>(ob, d, drho, jx, jy, jz, Pq, terms);
+      if (ob.kind == OBJ_MEA) {
+        mea_terms<Q>(g, ob, x, y, z, r, fs, terms);
+      } else {
+        double Pq[6];
+        neq_flux<Q, double>(fs, drho, jx, jy, jz, ir, Pq);
+        objective_terms<Q>(ob, d, drho, jx, jy, jz, Pq, terms);
+      }
 #pragma unroll
       for (int m = 0; m < Coef<Q>::N; ++m) src[m * ob.rplane + r] = terms[m];
     }
@@ -997,6 +1068,10 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     for (int m = 0; m < 1 + D + L::NSYM; ++m) a[m] = (T)src[(Coef<Q>::A0 + m) * ob.rplane + r];
 #pragma unroll
     for (int i = 0; i < Q; ++i) lam[i] -= quad_eval<Q, T>(a, i);
+    if (ob.kind == OBJ_MEA) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[i] -= (T)mea_g<Q>(g, ob, x, y, z, r, i);
+    }
   }
 
   if (!ODD) {

@@ -47,6 +47,7 @@ ObjBox make_obj(const hlbm_lattice_s* L) {
   o.u0 = L->u0;
   o.p0 = L->p0;
   o.tau0 = L->desc.tau;
+  o.flag = L->mea_flag;
   return o;
 }
 
@@ -141,6 +142,25 @@ hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
   else
     k_cylinder<float><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (float*)L->dpor, xc, yc, D,
                                                               noise_dev, mode, box_half, d_solid);
+  return hipGetLastError();
+}
+
+hipError_t launch_mea_flags(hlbm_lattice_s* L) {
+  const Geo g = make_geo(L);
+  const ObjBox ob = make_obj(L);
+  const bool f64 = L->desc.precision == HLBM_FP64;
+  unsigned char* fl = L->mea_flag;
+  if (L->desc.stencil == HLBM_D2Q9) {
+    if (f64)
+      k_mea_flags<9, double><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const double*)L->dpor, fl);
+    else
+      k_mea_flags<9, float><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const float*)L->dpor, fl);
+  } else {
+    if (f64)
+      k_mea_flags<19, double><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const double*)L->dpor, fl);
+    else
+      k_mea_flags<19, float><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const float*)L->dpor, fl);
+  }
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ D2Q9, D3Q19 = 0, 1
 FP64, FP32, FP16S = 0, 1, 2
 BC_PERIODIC, BC_WALLS, BC_INLET_OUTLET = 0, 1, 2
 INLET_UNIFORM, INLET_PARABOLIC = 1, 2
-OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM = 0, 1, 2
+OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM, OBJ_MEA = 0, 1, 2, 3
 TURB_FROZEN, TURB_DIFFERENTIATED = 0, 1
 SOURCE_STEADY, SOURCE_MEAN = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
