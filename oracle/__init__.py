@@ -73,6 +73,10 @@ def _load():
         "orc_set_objective": (C.c_int, [vp, C.c_int, _IP, _IP, C.c_double, C.c_double]),
         "orc_objective": (C.c_double, [vp]),
         "orc_mea_surface": (C.c_int, [vp, vp]),
+        "orc_tangent_seed": (C.c_int, [vp]),
+        "orc_tangent_step": (C.c_int, [vp, _DP, C.c_long]),
+        "orc_tangent_objective": (C.c_double, [vp, _DP]),
+        "orc_get_tangent": (C.c_int, [vp, _DP]),
         "orc_mea_source": (C.c_int, [vp, _DP]),
         "orc_window_reset": (None, [vp]),
         "orc_window_sample": (None, [vp]),
@@ -295,6 +299,24 @@ class Lattice:
 
     def objective(self) -> float:
         return self._lib.orc_objective(self._h)
+
+    # --- forward tangent (App. C)
+    def tangent_seed(self):
+        self._lib.orc_tangent_seed(self._h)
+
+    def tangent_step(self, v, n=1):
+        self._v = _f64(np.ravel(v))
+        if self._lib.orc_tangent_step(self._h, self._v, n) != 0:
+            raise ValueError("tangent not seeded")
+
+    def tangent_objective(self, v) -> float:
+        return self._lib.orc_tangent_objective(self._h, _f64(np.ravel(v)))
+
+    def tangent(self) -> np.ndarray:
+        out = np.zeros(self.q * self.n)
+        if self._lib.orc_get_tangent(self._h, out) != 0:
+            raise ValueError("tangent not seeded")
+        return out.reshape(self.q, self.n)
 
     def mea_surface(self) -> np.ndarray:
         """Surface flags of J_MEA (set_objective(OBJ_MEA, ...) first)."""

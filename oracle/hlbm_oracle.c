@@ -69,6 +69,10 @@ struct orc_lattice {
   double* phi;   /* [n*q] adjoint on post-collision slots */
   double* phiv;  /* [n*q] adjoint on outlet virtual slots */
   double* lam;   /* [n*q] */
+  /* forward tangent fdot = (df/dd) v (App. C) */
+  double* fdot;  /* [n*q] */
+  double* tpost; /* [n*q] post-collision tangent */
+  double* tvpost;/* [n*q] outlet virtual-column tangent */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -588,6 +592,7 @@ void orc_destroy(orc_lattice* L) {
   free(L->src); free(L->dst); free(L->vdst);
   free(L->fsum); free(L->gsum); free(L->dJdd_sum); free(L->tau_sum);
   free(L->jac); free(L->vjac); free(L->dcdd); free(L->gsrc); free(L->dJdd);
+  free(L->fdot); free(L->tpost); free(L->tvpost);
   free(L->phi); free(L->phiv); free(L->lam);
   free(L);
 }
@@ -1143,5 +1148,105 @@ int orc_apply_stream_transpose(const orc_lattice* L, const double* in, double* o
     out[(long)i * L->n + c] = (ds >= 0) ? in[(ds % q) * L->n + ds / q] : 0.0;
     vout[(long)i * L->n + c] = (vs >= 0) ? in[(vs % q) * L->n + vs / q] : 0.0;
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward tangent (App. C): the directional derivative fdot = (df/dd) v of  */
+/* the primal trajectory, carried along with it from fdot = 0 at the seeding */
+/* moment.  Each step: fdot* = (dC/df) fdot + (dC/dd) v at every collided    */
+/* cell, the outlet's virtual values get (dV/df) fdot, the pinned inlet 0,   */
+/* then the same streaming map as f.  dJ(t)/dd . v = sum dJ/df . fdot +      */
+/* dJ/dd v.  The closure enters through its exact Jacobian (tau_eff depends  */
+/* on f, not on d).                                                          */
+/* ------------------------------------------------------------------------ */
+
+int orc_tangent_seed(orc_lattice* L) {
+  long nq = L->n * L->q;
+  if (!L->fdot) {
+    L->fdot = (double*)calloc(nq, sizeof(double));
+    L->tpost = (double*)calloc(nq, sizeof(double));
+    L->tvpost = (double*)calloc(nq, sizeof(double));
+  }
+  memset(L->fdot, 0, sizeof(double) * nq);
+  return 0;
+}
+
+int orc_tangent_step(orc_lattice* L, const double* v, long nsteps) {
+  if (!L->fdot) return -1;
+  stencil_t s = lat_stencil(L);
+  int q = s.q;
+  for (long t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < L->n; ++c) {
+      double A[QMAX * QMAX], B[QMAX * QMAX], dc[QMAX];
+      const double* fc = L->f + c * q;
+      const double* td = L->fdot + c * q;
+      if (is_inlet(L, c)) {
+        for (int i = 0; i < q; ++i) L->tpost[c * q + i] = 0.0;
+        continue;
+      }
+      jacobian_s(&s, fc, L->d[c], L->p.tau, L->p.cs, ORC_TURB_DIFFERENTIATED, 0.0, A);
+      dcdd_s(&s, fc, L->d[c], tau_eff_s(&s, fc, L->p.tau, L->p.cs), dc);
+      for (int jj = 0; jj < q; ++jj) {
+        double acc = dc[jj] * v[c];
+        for (int i = 0; i < q; ++i) acc += A[jj * q + i] * td[i];
+        L->tpost[c * q + jj] = acc;
+      }
+      if (is_outlet(L, c)) {
+        outlet_jacobian_s(&s, fc, B);
+        for (int jj = 0; jj < q; ++jj) {
+          double acc = 0.0;
+          for (int i = 0; i < q; ++i) acc += B[jj * q + i] * td[i];
+          L->tvpost[c * q + jj] = acc;
+        }
+      }
+    }
+    step_once(L);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < L->n; ++c) {
+      for (int i = 0; i < q; ++i) {
+        long sidx = L->src[c * q + i];
+        double val;
+        if (sidx >= 0)
+          val = L->tpost[sidx];
+        else if (sidx == -1)
+          val = 0.0; /* pinned inlet */
+        else
+          val = L->tvpost[-2 - sidx];
+        L->fdot[c * q + i] = val;
+      }
+    }
+  }
+  return 0;
+}
+
+double orc_tangent_objective(const orc_lattice* L, const double* v) {
+  if (!L->fdot || !L->obj_set) return 0.0;
+  stencil_t s = lat_stencil(L);
+  int q = s.q;
+  double acc = 0.0;
+  if (L->obj_kind == ORC_OBJ_MEA) {
+    double* g = (double*)malloc(sizeof(double) * L->n * q);
+    mea_source_slots(L, g);
+    for (long k = 0; k < L->n * q; ++k) acc += g[k] * L->fdot[k];
+    free(g);
+    return acc;
+  }
+  double g[QMAX];
+  for (long c = 0; c < L->n; ++c) {
+    if (!in_region(L, c)) continue;
+    const double* fc = L->f + c * q;
+    dJdf_s(&s, L->obj_kind, fc, L->d[c], L->p.tau, L->u0, L->p0, g);
+    for (int i = 0; i < q; ++i) acc += g[i] * L->fdot[c * q + i];
+    acc += dJdd_s(&s, L->obj_kind, fc, L->d[c], L->p.tau) * v[c];
+  }
+  return acc;
+}
+
+int orc_get_tangent(const orc_lattice* L, double* fdot) {
+  if (!L->fdot) return -1;
+  for (long c = 0; c < L->n; ++c)
+    for (int i = 0; i < L->q; ++i) fdot[(long)i * L->n + c] = L->fdot[c * L->q + i];
   return 0;
 }

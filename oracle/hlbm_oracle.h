@@ -112,6 +112,14 @@ long orc_adjoint_solve(orc_lattice* L, long max_iters, double tol, long check_ev
 int orc_get_adjoint(const orc_lattice* L, double* phi);
 int orc_gradient(const orc_lattice* L, double* g);
 
+/* Forward tangent (App. C): fdot = (df/dd) v along the primal trajectory.
+ * seed: fdot = 0 at the current state; step: advances f and fdot together;
+ * objective: dJ(t)/dd . v of the current objective at the current state. */
+int orc_tangent_seed(orc_lattice* L);
+int orc_tangent_step(orc_lattice* L, const double* v, long nsteps);
+double orc_tangent_objective(const orc_lattice* L, const double* v);
+int orc_get_tangent(const orc_lattice* L, double* fdot);
+
 /* Per-cell building blocks (exposed for the pin tests). */
 void orc_stencil(int stencil, int* q, int* c /* 3*q */, double* w, int* opp);
 void orc_equilibrium(int stencil, double rho, const double* v, double* feq);
