@@ -217,6 +217,22 @@ hlbm_status hlbm_window_count(hlbm_lattice lat, int64_t* samples);
 /* which = 0: J of the current state; which = 1: window mean of J. */
 hlbm_status hlbm_get_objective(hlbm_lattice lat, int32_t which, double* J);
 
+/* ---- forward tangent (App. C) -------------------------------------------- */
+
+/* The exact transient sensitivity of the instantaneous objective along a
+ * porosity direction v (App. C, where it diverges for the unsteady flow):
+ * advances n_steps primal steps from the current state together with
+ * fdot = (df/dd) v, seeded fdot = 0 at the call (the current state is taken
+ * as independent of d), and every record_every steps writes J(t) and
+ * dJ(t)/dd . v = dJ/df . fdot + dJ/dd v to out[2r], out[2r + 1] (host
+ * memory, floor(n_steps / record_every) pairs).  v[n] is host or device
+ * memory per mem.  The primal state, parity and step count advance as with
+ * hlbm_run_primal (no window accumulation, no probe).  FP64 lattices
+ * without the Smagorinsky closure.  Errors: INVALID (precision, closure,
+ * sizes, null output), STATE (no objective), OOM, DEVICE. */
+hlbm_status hlbm_run_tangent(hlbm_lattice lat, const double* v, int64_t n, int32_t mem,
+                             int64_t n_steps, int64_t record_every, double* out);
+
 /* ---- adjoint and gradient (rows a7, a8, a9) ------------------------------ */
 
 /* Freeze the Jacobian data (row a7) and iterate the adjoint sweep (row a8).

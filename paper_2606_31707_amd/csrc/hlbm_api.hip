@@ -315,7 +315,8 @@ void hlbm_destroy(hlbm_lattice L) {
   (void)hipStreamSynchronize(L->stream);
   void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
-                  L->red, L->usnap, L->probe_buf, L->mea_flag};
+                  L->red, L->usnap, L->probe_buf, L->mea_flag, L->tan_f, L->tan_ghost,
+                  L->tan_v, L->tan_rec};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
   if (L->ev0) (void)hipEventDestroy(L->ev0);
@@ -613,6 +614,55 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
   if (steady_tol > 0.0 && !converged) result = HLBM_W_NOT_CONVERGED;
   L->adj_ready = 0;
   return result;
+}
+
+hlbm_status hlbm_run_tangent(hlbm_lattice L, const double* v, int64_t n, int32_t mem, int64_t n_steps,
+                             int64_t record_every, double* out) {
+  CHECK_LAT(L);
+  if (L->desc.precision != HLBM_FP64) return fail(HLBM_E_INVALID, "the tangent runs on FP64 lattices");
+  if (L->desc.smagorinsky_cs > 0.0) return fail(HLBM_E_INVALID, "the tangent has no Smagorinsky closure");
+  if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
+  if (!v || n != L->n) return fail(HLBM_E_INVALID, "v needs %lld values", (long long)L->n);
+  if (n_steps < 0 || record_every < 1) return fail(HLBM_E_INVALID, "bad step counts");
+  const int64_t nrec = n_steps / record_every;
+  if (nrec > 0 && !out) return fail(HLBM_E_INVALID, "null output");
+  hlbm_status s;
+  if ((s = ensure_mea(L)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->tan_f, sizeof(double) * L->q * L->plane)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->tan_ghost, sizeof(double) * L->q * L->gplane)) != HLBM_OK) return s;
+  if ((s = dev_alloc((void**)&L->tan_v, sizeof(double) * L->plane)) != HLBM_OK) return s;
+  if (nrec > L->tan_rec_cap) {
+    dev_free(L->tan_rec);
+    L->tan_rec = nullptr;
+    L->tan_rec_cap = 0;
+    if ((s = dev_alloc((void**)&L->tan_rec, sizeof(double) * 2 * nrec)) != HLBM_OK) return s;
+    L->tan_rec_cap = nrec;
+  }
+  HIP_TRY(hipMemcpyAsync(L->tan_v, v, sizeof(double) * L->n,
+                         mem == HLBM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, L->stream));
+  // seeding: fdot = 0 at the current state
+  HIP_TRY(hipMemsetAsync(L->tan_f, 0, sizeof(double) * L->q * L->plane, L->stream));
+  HIP_TRY(hipMemsetAsync(L->tan_ghost, 0, sizeof(double) * L->q * L->gplane, L->stream));
+  const int64_t nb = n_blocks(L);
+  int64_t r = 0;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    HIP_TRY(launch_tangent_step(L));
+    L->parity ^= 1;
+    L->steps += 1;
+    if ((k + 1) % record_every == 0) {
+      int nbl = 0;
+      HIP_TRY(launch_tangent_objective(L, L->red, &nbl));
+      HIP_TRY(launch_finalize_sum(L, L->red, nbl, L->tan_rec + 2 * r));
+      HIP_TRY(launch_finalize_sum(L, L->red + nb, nbl, L->tan_rec + 2 * r + 1));
+      r += 1;
+    }
+  }
+  if (nrec > 0)
+    HIP_TRY(hipMemcpyAsync(out, L->tan_rec, sizeof(double) * 2 * nrec, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  L->adj_ready = 0;
+  L->usnap_valid = 0;
+  return HLBM_OK;
 }
 
 hlbm_status hlbm_get_objective(hlbm_lattice L, int32_t which, double* J) {

@@ -72,6 +72,14 @@ struct hlbm_lattice_s {
   double prof_ms[3] = {0.0, 0.0, 0.0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
+  // forward tangent (FP64): fdot in the AA layout, its outlet buffer, v,
+  // and the device record of (J, dJ/dd . v)
+  double* tan_f = nullptr;
+  double* tan_ghost = nullptr;
+  double* tan_v = nullptr;
+  double* tan_rec = nullptr;
+  int64_t tan_rec_cap = 0;
+
   // velocity probe
   int64_t probe_cell = -1;
   double* probe_buf = nullptr;
@@ -117,6 +125,8 @@ hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
                            const double* noise_dev, int mode, double box_half, double d_solid);
 hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev);
 hipError_t launch_mea_flags(hlbm_lattice_s* L);
+hipError_t launch_tangent_step(hlbm_lattice_s* L);
+hipError_t launch_tangent_objective(hlbm_lattice_s* L, double* partials, int* nblocks);
 hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);
 hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev);

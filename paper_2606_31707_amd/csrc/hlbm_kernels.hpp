@@ -453,6 +453,191 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
   primal_cell<Q, S, ODD, ACC>(g, c, ob, A, dpor, ghost, acc, x, y, z);
 }
 
+// =========================================================================
+// forward tangent (App. C): one primal step of BGK-HLBM together with its
+// directional derivative fdot = (df/dd) v (FP64, no closure).  The tangent
+// lives in a second AA population array and follows exactly the same
+// propagation and boundaries; the pinned inlet has a zero tangent and the
+// outlet's virtual values V = f^eq(1, u) carry dV = (dV/du) du.
+// =========================================================================
+template <int Q, bool ODD>
+__device__ __forceinline__ void tangent_cell(const Geo& g, const Coll& c, double* __restrict__ A,
+                                             double* __restrict__ At, const double* __restrict__ dpor,
+                                             const double* __restrict__ v, double* __restrict__ ghost,
+                                             double* __restrict__ ghostt, const int x, const int y,
+                                             const int z) {
+  using L = Lat<Q>;
+  const int64_t cell = cell_of(g, x, y, z);
+  const bool inout = (g.bcx == BC_INOUT);
+  double s[Q], t[Q];
+  if (inout && x == 0) {
+    inlet_state<Q, double>(g, y, s);
+    if (!ODD) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        A[L::opp[k] * g.plane + cell] = s[k];
+        At[L::opp[k] * g.plane + cell] = 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        push<Q, double>(g, A, x, y, z, cell, k, s[k]);
+        push<Q, double>(g, At, x, y, z, cell, k, 0.0);
+      }
+    }
+    return;
+  }
+  const bool interior = ODD && interior_cell<Q>(g, x, y, z);
+  if (!ODD) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      s[k] = A[k * g.plane + cell];
+      t[k] = At[k * g.plane + cell];
+    }
+  } else if (interior) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t o = L::opp[k] * g.plane + cell - nb_offset<Q>(g, k);
+      s[k] = A[o];
+      t[k] = At[o];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      s[k] = pull<Q, double, double>(g, A, ghost, x, y, z, cell, k);
+      t[k] = pull<Q, double, double>(g, At, ghostt, x, y, z, cell, k);
+    }
+  }
+  double drho, jx, jy, jz, tr, tjx, tjy, tjz;
+  cell_moments<Q, double>(s, drho, jx, jy, jz);
+  cell_moments<Q, double>(t, tr, tjx, tjy, tjz);
+  const double rho = 1.0 + drho, ir = 1.0 / rho;
+  const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  // du = (dj - u drho) / rho
+  const double dux = (tjx - ux * tr) * ir, duy = (tjy - uy * tr) * ir, duz = (tjz - uz * tr) * ir;
+  const double d = dpor[cell], vd = v[cell];
+  // u~ = d u, du~ = d du + u v
+  const double tx = d * ux, ty = d * uy, tz = d * uz;
+  const double dtx = d * dux + vd * ux, dty = d * duy + vd * uy, dtz = d * duz + vd * uz;
+  const double tt = tx * tx + ty * ty + tz * tz;
+  const double dtt = 2.0 * (tx * dtx + ty * dty + tz * dtz);
+  const double omega = c.omega0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double cu = L::cx[k] * tx + L::cy[k] * ty + L::cz[k] * tz;
+    const double dcu = L::cx[k] * dtx + L::cy[k] * dty + L::cz[k] * dtz;
+    const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * tt;
+    const double feqs = L::w[k] * (drho + rho * poly);
+    const double dfeqs = L::w[k] * (tr + tr * poly + rho * (3.0 * dcu + 9.0 * cu * dcu - 1.5 * dtt));
+    const double fk = 3.0 * L::w[k] * (L::cx[k] * c.force[0] + L::cy[k] * c.force[1] + L::cz[k] * c.force[2]);
+    s[k] = s[k] + omega * (feqs - s[k]) + fk;
+    t[k] = t[k] + omega * (dfeqs - t[k]);
+  }
+  const bool outlet = inout && (x == g.nx - 1);
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double duu = 2.0 * (ux * dux + uy * duy + uz * duz);
+  if (!ODD) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      A[L::opp[k] * g.plane + cell] = s[k];
+      At[L::opp[k] * g.plane + cell] = t[k];
+    }
+    if (outlet) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] != -1) continue;
+        const double cu = L::cx[k] * ux + L::cy[k] * uy + L::cz[k] * uz;
+        const double dcu = L::cx[k] * dux + L::cy[k] * duy + L::cz[k] * duz;
+        const int64_t o = k * g.gplane + y + (int64_t)g.ny * z;
+        ghost[o] = L::w[k] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        ghostt[o] = L::w[k] * (3.0 * dcu + 9.0 * cu * dcu - 1.5 * duu);
+      }
+    }
+  } else if (interior) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t o = k * g.plane + cell + nb_offset<Q>(g, k);
+      A[o] = s[k];
+      At[o] = t[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      push<Q, double>(g, A, x, y, z, cell, k, s[k]);
+      push<Q, double>(g, At, x, y, z, cell, k, t[k]);
+    }
+    if (outlet) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] != -1) continue;
+        int vx = x, vy = y + L::cy[k], vz = z + L::cz[k];
+        if (classify(g, vx, vy, vz) != NB_CELL) continue;
+        const double cu = L::cx[k] * ux + L::cy[k] * uy + L::cz[k] * uz;
+        const double dcu = L::cx[k] * dux + L::cy[k] * duy + L::cz[k] * duz;
+        const int64_t o = k * g.plane + cell_of(g, vx, vy, vz);
+        A[o] = L::w[k] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        At[o] = L::w[k] * (3.0 * dcu + 9.0 * cu * dcu - 1.5 * duu);
+      }
+    }
+  }
+}
+
+template <int Q, bool ODD>
+__global__ __launch_bounds__(256) void k_tangent(const Geo g, const Coll c, double* __restrict__ A,
+                                                 double* __restrict__ At, const double* __restrict__ dpor,
+                                                 const double* __restrict__ v, double* __restrict__ ghost,
+                                                 double* __restrict__ ghostt) {
+  SWEEP_PROLOGUE
+  if (!valid) return;
+  tangent_cell<Q, ODD>(g, c, A, At, dpor, v, ghost, ghostt, x, y, z);
+}
+
+// J(t) and dJ(t)/dd . v over the objective region: dJ/df . fdot from the
+// coefficients a0 + a1.xi + a2:xi xi (J_MEA: its constant source) plus
+// dJ/dd v.  Block partials: J at partials[b], the tangent at partials[nb + b].
+template <int Q>
+__global__ __launch_bounds__(256) void k_tangent_objective(const Geo g, const ObjBox ob,
+                                                           const double* __restrict__ A,
+                                                           const double* __restrict__ At,
+                                                           const double* __restrict__ ghost,
+                                                           const double* __restrict__ ghostt, int parity,
+                                                           const double* __restrict__ dpor,
+                                                           const double* __restrict__ v,
+                                                           double* __restrict__ partials) {
+  using C = Coef<Q>;
+  __shared__ double lds[4];
+  CELL_PROLOGUE
+  double vj = 0.0, vt = 0.0;
+  int64_t r;
+  if (valid && region_index<Q>(ob, x, y, z, r)) {
+    double s[Q], t[Q];
+    load_state<Q, double, double>(g, A, ghost, parity, x, y, z, cell, s);
+    load_state<Q, double, double>(g, At, ghostt, parity, x, y, z, cell, t);
+    double terms[C::N];
+    if (ob.kind == OBJ_MEA) {
+      mea_terms<Q>(g, ob, x, y, z, r, s, terms);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) vt += mea_g<Q>(g, ob, x, y, z, r, k) * t[k];
+    } else {
+      double dr, jx, jy, jz, P[6];
+      cell_moments<Q, double>(s, dr, jx, jy, jz);
+      neq_flux<Q, double>(s, dr, jx, jy, jz, 1.0 / (1.0 + dr), P);
+      objective_terms<Q>(ob, dpor[cell], dr, jx, jy, jz, P, terms);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) vt += quad_eval<Q, double>(terms + C::A0, k) * t[k];
+      vt += terms[C::DJDD] * v[cell];
+    }
+    vj = terms[C::J];
+  }
+  const double a = block_sum256(vj, lds);
+  const double b = block_sum256(vt, lds);
+  if (threadIdx.x + blockDim.x * threadIdx.y == 0) {
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    partials[linear_block()] = a;
+    partials[nb + linear_block()] = b;
+  }
+}
+
 // Packed launch: one workgroup grid covering several lattices of one stencil
 // and precision (member m owns blocks [first_block, first_block + tiles)).
 // Each member runs exactly the per-cell code of k_primal, so its result does

@@ -164,6 +164,45 @@ hipError_t launch_mea_flags(hlbm_lattice_s* L) {
   return hipGetLastError();
 }
 
+hipError_t launch_tangent_step(hlbm_lattice_s* L) {
+  const Geo g = make_geo(L);
+  const Coll c = make_coll(L);
+  double* A = (double*)L->f;
+  double* gh = (double*)L->ghost;
+  const double* dp = (const double*)L->dpor;
+  const dim3 grid = sweep_grid(L);
+  const bool odd = L->parity != 0;
+  if (L->desc.stencil == HLBM_D2Q9) {
+    if (odd)
+      k_tangent<9, true><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+    else
+      k_tangent<9, false><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+  } else {
+    if (odd)
+      k_tangent<19, true><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+    else
+      k_tangent<19, false><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_objective(hlbm_lattice_s* L, double* partials, int* nblocks) {
+  const dim3 grid = cell_grid(L);
+  *nblocks = (int)(grid.x * grid.y * grid.z);
+  const Geo g = make_geo(L);
+  const ObjBox ob = make_obj(L);
+  const double* A = (const double*)L->f;
+  const double* gh = (const double*)L->ghost;
+  const double* dp = (const double*)L->dpor;
+  if (L->desc.stencil == HLBM_D2Q9)
+    k_tangent_objective<9><<<grid, kBlock, 0, L->stream>>>(g, ob, A, L->tan_f, gh, L->tan_ghost, L->parity, dp,
+                                                          L->tan_v, partials);
+  else
+    k_tangent_objective<19><<<grid, kBlock, 0, L->stream>>>(g, ob, A, L->tan_f, gh, L->tan_ghost, L->parity, dp,
+                                                           L->tan_v, partials);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev) {
   if (L->desc.precision == HLBM_FP64)
     k_set_porosity<double><<<cell_grid(L), kBlock, 0, L->stream>>>(make_geo(L), (double*)L->dpor, d_dev,

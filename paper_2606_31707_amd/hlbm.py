@@ -38,7 +38,7 @@ EXPORTS = [
     "hlbm_get_adjoint", "hlbm_get_field", "hlbm_synchronize", "hlbm_profile_enable",
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
     "hlbm_set_probe", "hlbm_get_probe", "hlbm_reconfigure", "hlbm_group_create", "hlbm_group_destroy",
-    "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize",
+    "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize", "hlbm_run_tangent",
 ]
 
 GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH):
         "hlbm_group_step": (i32, [vp, i64]),
         "hlbm_group_synchronize": (i32, [vp]),
         "hlbm_get_probe": (i32, [vp, vp, i64, P(i64)]),
+        "hlbm_run_tangent": (i32, [vp, vp, i64, i32, i64, i64, vp]),
         "hlbm_bytes_per_update": (i32, [vp, P(dbl), P(dbl), P(dbl)]),
         "hlbm_status_string": (C.c_char_p, [i32]),
         "hlbm_last_error": (C.c_char_p, []),
@@ -286,6 +287,16 @@ class Lattice:
 
     def step(self, n=1, accumulate=False):
         return self.run_primal(n, accumulate)
+
+    def run_tangent(self, v, n_steps, record_every=1):
+        """Forward tangent along v from the current state: returns an array
+        [records, 2] of (J(t), dJ(t)/dd . v)."""
+        p, n, mem, _keep = _arr_in(v, self.n)
+        nrec = int(n_steps) // int(record_every)
+        out = np.zeros(2 * max(nrec, 1))
+        _check(self._lib.hlbm_run_tangent(self._h, p, n, mem, int(n_steps), int(record_every),
+                                          out.ctypes.data_as(C.c_void_p)))
+        return out[: 2 * nrec].reshape(nrec, 2)
 
     def window_reset(self):
         _check(self._lib.hlbm_window_reset(self._h))

@@ -1,0 +1,81 @@
+"""GPU parity of the forward tangent (App. C): J(t) and dJ(t)/dd . v along
+the primal trajectory, GPU (hand-derived tangent of the BGK-HLBM step)
+against the oracle (the pinned per-cell Jacobians applied to fdot), from a
+common state, over both AA parities and a re-seeding; plus a GPU-only
+central-difference check of the transient derivative."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_31707_amd import inputs as I
+from tests.pairs import Spec, make_gpu, make_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def spec(kind, stencil=O.D2Q9):
+    if stencil == O.D3Q19:
+        return Spec(stencil=O.D3Q19, nx=40, ny=18, nz=5, tau=0.6, u_in=0.05, cyl=(13.0, 8.5, 6.0),
+                    obj=(O.OBJ_FFA, (30, 0, 0), (30, 17, 4), 0.05))
+    w = I.channel_re20()
+    objs = {O.OBJ_FFA: (O.OBJ_FFA, w.lo, w.hi, 0.05), O.OBJ_DISS: (O.OBJ_DISS, (2, 0, 0), (200, 40, 0), 0.0),
+            O.OBJ_MEA: (O.OBJ_MEA, (30, 8, 0), (50, 32, 0), math.pi * w.D)}
+    return Spec(nx=w.nx, ny=w.ny, tau=0.56, u_in=0.05, cyl=(w.xc, w.yc, w.D), obj=objs[kind])
+
+
+def direction(L, seed=3):
+    d = L.porosity()
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(L.n) * (d > 0.01) * (d < 0.99)
+    return v / np.linalg.norm(v)
+
+
+def oracle_series(L, v, n):
+    out = np.zeros((n, 2))
+    for t in range(n):
+        L.tangent_step(v, 1)
+        out[t] = L.objective(), L.tangent_objective(v)
+    return out
+
+
+@pytest.mark.parametrize("kind,stencil", [(O.OBJ_FFA, O.D2Q9), (O.OBJ_DISS, O.D2Q9), (O.OBJ_MEA, O.D2Q9),
+                                          (O.OBJ_FFA, O.D3Q19)])
+def test_tangent_series_matches_oracle(kind, stencil):
+    s = spec(kind, stencil)
+    say("tangent parity", kind, stencil)
+    L, G = make_oracle(s), make_gpu(s)
+    L.step(300)
+    G.set_populations(L.populations())
+    v = direction(L)
+    for n in (151, 100):  # the second run starts on the other AA parity
+        L.tangent_seed()
+        ref = oracle_series(L, v, n)
+        got = G.run_tangent(v, n, 1)
+        eJ = np.abs(got[:, 0] - ref[:, 0]).max() / np.abs(ref[:, 0]).max()
+        eT = np.abs(got[:, 1] - ref[:, 1]).max() / np.abs(ref[:, 1]).max()
+        print(f"tangent parity ({n} steps): J {eJ:.3e}, dJ/dd.v {eT:.3e}", flush=True)
+        assert eJ < 1e-11 and eT < 1e-11
+
+
+def test_tangent_against_gpu_central_differences():
+    s = spec(O.OBJ_DISS)
+    say("tangent FD")
+    G = make_gpu(s)
+    G.run_primal(300)
+    f0 = G.populations()
+    d0 = G.porosity()
+    v = direction(G, 4)
+    n = 120
+    tj = G.run_tangent(v, n, n)[-1, 1]
+    eps = 1e-6
+    J = []
+    for sgn in (1.0, -1.0):
+        G.set_porosity(d0 + sgn * eps * v)
+        G.set_populations(f0)
+        G.run_primal(n)
+        J.append(G.objective(0))
+    fd = (J[0] - J[1]) / (2 * eps)
+    print(f"tangent {tj:.12e} vs FD {fd:.12e}", flush=True)
+    assert abs(tj - fd) < 1e-6 * abs(fd)
