@@ -479,11 +479,15 @@ def report_validation3d(steps: int, adj_iters: int, fd_scale: float, fd_points: 
                       "grad_cosine": float(a @ b / np.linalg.norm(a) / np.linalg.norm(b)),
                       "surface_rel_max": float(np.abs(a[ring] - b[ring]).max() / np.abs(b[ring]).max())}
 
-    # central differences of the converged FP64 drag on a scaled copy
-    ws = I.scaled(w, fd_scale)
+    # central differences of the converged FP64 drag on a scaled copy at
+    # Re 20 (the 2D validation Reynolds number: a steady wake at this
+    # resolution; the coarser Re 40 copy does not settle)
+    from dataclasses import replace as _replace
+    ws = _replace(I.scaled(w, fd_scale), Re=20.0)
     G = make(ws, H.FP64)
     G.set_objective(H.OBJ_FFA, ws.lo, ws.hi, u0=ws.u0)
-    G.run_primal(400000, steady_tol=1e-13, check_every=500)
+    base_steps = G.run_primal(400000, steady_tol=1e-13, check_every=500)
+    log(f"validation3d FD base: {base_steps} steps to steady (tau {ws.tau:.4f})")
     d0 = G.porosity()
     f0 = G.populations()
     J0 = G.objective(0)
@@ -503,8 +507,9 @@ def report_validation3d(steps: int, adj_iters: int, fd_scale: float, fd_points: 
             d[c] += sgn * eps
             G.set_porosity(d)
             G.set_populations(f0)
-            G.run_primal(400000, steady_tol=1e-13, check_every=500)
+            ns = G.run_primal(400000, steady_tol=1e-13, check_every=500)
             vals.append(G.objective(0))
+            log(f"validation3d FD cell {c} ({sgn:+.0f}): {ns} steps")
         fdv = (vals[0] - vals[1]) / (2 * eps)
         fd.append({"cell": int(c), "angle_deg": float(np.degrees(np.arctan2(ys[c] - ws.yc, xs[c] - ws.xc))),
                    "adjoint": float(g[c]), "fd": fdv, "rel_err": abs(g[c] - fdv) / abs(fdv)})
@@ -512,8 +517,70 @@ def report_validation3d(steps: int, adj_iters: int, fd_scale: float, fd_points: 
     G.close()
     out = {"report": "validation3d", "workload": w.name, "steps": steps, "d_solid": w.d_solid,
            "surface_samples": len(ring), "forms": res, "fp32_vs_fp64": cmp,
-           "fd": {"workload": ws.name, "cells": ws.n, "J": J0, "eps": eps, "points": fd,
+           "fd": {"workload": ws.name, "Re": ws.Re, "tau": ws.tau, "cells": ws.n, "base_steps": base_steps,
+                  "J": J0, "eps": eps, "points": fd,
                   "max_rel_err": max(p_["rel_err"] for p_ in fd)}}
+    print(json.dumps(out), flush=True)
+
+
+def report_tangent(steps: int, late: int, record: int, blocks: int):
+    """App. C on the Re = 100 vortex street (1100 x 410, FP64, dissipation
+    box): the forward tangent dJ(t)/dd . v for a unit porosity change of one
+    cylinder-rim cell, seeded at t = 0 and again once shedding is developed;
+    its growth over time, its time average over the last ten periods against
+    the mean-flow adjoint's derivative of the time average."""
+    w = I.vortex_re100()
+    noise = I.porosity_noise(w)
+
+    def fresh():
+        G = H.Lattice(stencil=w.stencil, precision=H.FP64, nx=w.nx, ny=w.ny, tau=w.tau, bc_x=H.BC_INLET_OUTLET,
+                      bc_y=w.bc_y, inlet_profile=w.inlet_profile, u_in=w.u_max)
+        G.build_cylinder(w.xc, w.yc, w.D, noise=noise, noise_mode=w.noise_mode)
+        G.init_equilibrium()
+        G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
+        return G
+
+    G = fresh()
+    d = G.porosity()
+    x, y = np.arange(w.n) % w.nx, np.arange(w.n) // w.nx
+    rim = np.nonzero((d > 0.05) & (d < 0.95) & (x == int(w.xc)) & (y > w.yc))[0]
+    cell = int(rim[0])
+    v = np.zeros(w.n)
+    v[cell] = 1.0
+
+    def growth(rec):
+        b = np.array_split(np.abs(rec[:, 1]), blocks)
+        return [float(np.max(a)) for a in b]
+
+    t0 = time.perf_counter()
+    recA = G.run_tangent(v, steps, record)
+    log(f"tangent seeded at 0: {steps} steps ({time.perf_counter() - t0:.1f} s)")
+    G.close()
+    G = fresh()
+    G.set_probe(*w.extra["probe"], 0, late)
+    G.run_primal(late)
+    P = shedding_period(G.probe())
+    recB = G.run_tangent(v, steps - late, record)
+    log(f"tangent seeded at {late}: period {P}")
+    # mean-flow adjoint over the last ten periods of the same trajectory
+    G.close()
+    G = fresh()
+    W = int(round(10 * P)) if P else steps // 5
+    G.run_primal(steps - W)
+    G.run_primal(W, accumulate=True)
+    it, rr, _ = G.solve_adjoint(H.SOURCE_MEAN, max_iters=60000, tol=1e-6, check_every=1000)
+    gv = float(G.gradient()[cell])
+    nwin = max(1, W // record)
+    out = {"report": "tangent", "workload": w.name, "steps": steps, "record_every": record,
+           "cell": cell, "cell_xy": [int(x[cell]), int(y[cell])], "d_cell": float(d[cell]),
+           "shedding_period": P, "window_steps": W,
+           "seeded_at_0": {"max_abs_dJdd_per_block": growth(recA),
+                           "mean_over_window": float(recA[-nwin:, 1].mean()),
+                           "J_mean_over_window": float(recA[-nwin:, 0].mean())},
+           "seeded_at_%d" % late: {"max_abs_dJdd_per_block": growth(recB),
+                                   "mean_over_window": float(recB[-nwin:, 1].mean())},
+           "mean_flow_adjoint": {"dJmean_dd": gv, "iters": it, "residual": rr, "J_mean": G.window_objective()}}
+    G.close()
     print(json.dumps(out), flush=True)
 
 
@@ -531,7 +598,8 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d"], default=None,
+    ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d", "tangent"],
+                    default=None,
                     help="print a secondary measurement report instead of the benchmark line")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--fd-fields", type=int, default=2)
@@ -544,6 +612,9 @@ def main():
     ap.add_argument("--v3d-adjoint", type=int, default=60000)
     ap.add_argument("--v3d-fd-scale", type=float, default=1.0 / 3.0)
     ap.add_argument("--v3d-fd-points", type=int, default=4)
+    ap.add_argument("--tan-steps", type=int, default=200000)
+    ap.add_argument("--tan-late", type=int, default=150000)
+    ap.add_argument("--tan-record", type=int, default=50)
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--rate", type=float, default=2.0)
     ap.add_argument("--mem-cap-gib", type=float, default=16.0)
@@ -568,6 +639,9 @@ def main():
         return
     if args.report == "validation3d":
         report_validation3d(args.v3d_steps, args.v3d_adjoint, args.v3d_fd_scale, args.v3d_fd_points)
+        return
+    if args.report == "tangent":
+        report_tangent(args.tan_steps, args.tan_late, args.tan_record, 20)
         return
     if args.report == "serving":
         report_serving(args.queries, args.rate, args.mem_cap_gib, args.tick, args.slots)

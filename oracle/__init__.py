@@ -23,6 +23,7 @@ INLET_UNIFORM, INLET_PARABOLIC = 1, 2
 OBJ_FFA, OBJ_DISS, OBJ_MOMENTUM, OBJ_MEA = 0, 1, 2, 3
 TURB_FROZEN, TURB_DIFFERENTIATED = 0, 1
 NOISE_NONE, NOISE_RIM, NOISE_BOX = 0, 1, 2
+COLL_BGK, COLL_HRR = 0, 1
 
 
 class _Params(C.Structure):
@@ -39,6 +40,7 @@ class _Params(C.Structure):
         ("inlet_profile", C.c_int),
         ("u_in", C.c_double),
         ("force", C.c_double * 3),
+        ("collision", C.c_int),
     ]
 
 
@@ -74,6 +76,11 @@ def _load():
         "orc_objective": (C.c_double, [vp]),
         "orc_mea_surface": (C.c_int, [vp, vp]),
         "orc_tangent_seed": (C.c_int, [vp]),
+        "orc_hrr_collide_cell": (None, [C.c_int, _DP, C.c_double, C.c_double, C.c_double, vp, _DP]),
+        "orc_hrr_jacobian_cell": (None, [C.c_int, _DP, C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                         _DP]),
+        "orc_hrr_dcdd_cell": (None, [C.c_int, _DP, C.c_double, C.c_double, C.c_double, C.c_int, C.c_double,
+                                     _DP]),
         "orc_tangent_step": (C.c_int, [vp, _DP, C.c_long]),
         "orc_tangent_objective": (C.c_double, [vp, _DP]),
         "orc_get_tangent": (C.c_int, [vp, _DP]),
@@ -149,6 +156,29 @@ def tau_eff(kind, f, tau0, cs) -> float:
     return _load().orc_tau_eff(kind, _f64(f), tau0, cs)
 
 
+def hrr_collide_cell(kind, f, d, tau0, cs=0.0, force=None) -> np.ndarray:
+    f = _f64(f)
+    out = np.zeros_like(f)
+    fo = None if force is None else _f64(np.resize(np.asarray(force, float), 3))
+    _load().orc_hrr_collide_cell(kind, f, d, tau0, cs, _ptr(fo), out)
+    return out
+
+
+def hrr_jacobian_cell(kind, f, d, tau_a, cs=0.0, turb=TURB_DIFFERENTIATED, tau_frozen=0.0) -> np.ndarray:
+    f = _f64(f)
+    q = len(f)
+    A = np.zeros(q * q)
+    _load().orc_hrr_jacobian_cell(kind, f, d, tau_a, cs, turb, tau_frozen, A)
+    return A.reshape(q, q)
+
+
+def hrr_dcdd_cell(kind, f, d, tau_a, cs=0.0, turb=TURB_DIFFERENTIATED, tau_frozen=0.0) -> np.ndarray:
+    f = _f64(f)
+    out = np.zeros(len(f))
+    _load().orc_hrr_dcdd_cell(kind, f, d, tau_a, cs, turb, tau_frozen, out)
+    return out
+
+
 def collide_cell(kind, f, d, tau0, cs=0.0, force=None) -> np.ndarray:
     f = _f64(f)
     out = np.zeros_like(f)
@@ -222,6 +252,7 @@ class Params:
     inlet_profile: int = INLET_PARABOLIC
     u_in: float = 0.03
     force: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    collision: int = 0   # COLL_BGK or COLL_HRR
 
 
 class Lattice:
@@ -230,7 +261,7 @@ class Lattice:
     def __init__(self, p: Params):
         lib = _load()
         cp = _Params(p.stencil, p.nx, p.ny, p.nz, p.tau, p.cs, p.bc_x, p.bc_y, p.bc_z,
-                     p.inlet_profile, p.u_in, (C.c_double * 3)(*p.force))
+                     p.inlet_profile, p.u_in, (C.c_double * 3)(*p.force), p.collision)
         h = lib.orc_create(C.byref(cp))
         if not h:
             raise ValueError(f"oracle rejected parameters {p}")

@@ -27,6 +27,7 @@
  */
 #include "hlbm_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -324,6 +325,141 @@ void orc_dcdd_cell(int stencil, const double* f, double d, double tau_used, doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* HRRLBM collision (Sec. 2.2, Eq. HRRLBM), read as:                         */
+/*   C_i = f_i^eq + (1 - 1/tau_eff) f_i^(1)                                  */
+/*   f_i^eq  = w_i [rho + 3 xi_i.rho u~ + (9/2) H2_i:rho u~u~                 */
+/*                  + (9/2) H3_i:rho u~u~u~],  u~ = d u                       */
+/*   f_i^(1) = w_i [3 xi_i.a1 + (9/2) H2_i:a2 + (9/2) H3_i:a3]                */
+/* with the Hermite coefficients of the non-equilibrium part f - f^eq:       */
+/*   a0 = 0, a1 = j - rho u~ = (1 - d) j, a2 = sum_i H2_i f_i - rho u~u~      */
+/*   (projections), a3_abg = u~_a a2_bg + u~_b a2_ag + u~_g a2_ab (recursive),*/
+/* H2_i = xi_i xi_i - I/3, and the third order restricted to the components  */
+/* H_aab = xi_b (xi_a^2 - 1/3), a != b, that the velocity set supports (each */
+/* enters H3:a with multiplicity 3).  tau_eff: the Smagorinsky closure on    */
+/* Pi of f^eq(rho, u) as for BGK.  Complex arithmetic: the exact Jacobian    */
+/* dC/df and dC/dd follow by complex-step differentiation.                   */
+/* ------------------------------------------------------------------------ */
+
+static const int H3_TYPES_2D[2][2] = {{0, 1}, {1, 0}};
+static const int H3_TYPES_3D[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+
+/* freeze: 0 -> tau_eff from the closure (or tau0 without it); 1 -> tau_frozen */
+static void hrr_collide_z(const stencil_t* s, const double complex* f, double complex d, double tau0,
+                          double cs, int freeze, double tau_frozen, const double* force,
+                          double complex* out) {
+  const int q = s->q, D = s->dim;
+  double complex drho = 0.0, j[3] = {0.0, 0.0, 0.0}, S[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) S[a][b] = 0.0;
+  for (int i = 0; i < q; ++i) {
+    double complex g = f[i] - s->w[i]; /* shifted: sum w = 1, sum w xi xi = I/3 */
+    drho += g;
+    for (int a = 0; a < 3; ++a) j[a] += s->c[i][a] * f[i];
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) S[a][b] += s->c[i][a] * s->c[i][b] * g;
+  }
+  double complex rho = 1.0 + drho, u[3], ut[3];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = j[a] / rho;
+    ut[a] = d * u[a];
+  }
+  double complex tau = tau0;
+  if (freeze) {
+    tau = tau_frozen;
+  } else if (cs > 0.0) {
+    double complex P2 = 0.0;
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) {
+        double complex Pi = S[a][b] - (a == b ? drho / 3.0 : 0.0) - j[a] * j[b] / rho;
+        P2 += Pi * Pi;
+      }
+    /* |Pi| = 0: no strain, tau_eff = tau0 and no derivative (as for BGK) */
+    double complex P = (creal(P2) > 0.0) ? csqrt(P2) : 0.0;
+    tau = 0.5 * (tau0 + csqrt(tau0 * tau0 + 18.0 * sqrt(2.0) * cs * cs * P));
+  }
+  double complex a2[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      a2[a][b] = (a < D && b < D) ? S[a][b] - (a == b ? drho / 3.0 : 0.0) - rho * ut[a] * ut[b] : 0.0;
+  const int nt = (D == 2) ? 2 : 6;
+  const int(*T)[2] = (D == 2) ? H3_TYPES_2D : H3_TYPES_3D;
+  for (int i = 0; i < q; ++i) {
+    const int* c = s->c[i];
+    double complex cu = 0.0, cj = 0.0, tt = 0.0;
+    for (int a = 0; a < D; ++a) {
+      cu += c[a] * ut[a];
+      cj += c[a] * j[a];
+      tt += ut[a] * ut[a];
+    }
+    double complex e2 = rho * (cu * cu - tt / 3.0), e3 = 0.0, n2 = 0.0, n3 = 0.0;
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) n2 += (c[a] * c[b] - (a == b ? 1.0 / 3.0 : 0.0)) * a2[a][b];
+    for (int t = 0; t < nt; ++t) {
+      const int a = T[t][0], b = T[t][1];
+      const double H = c[b] * (c[a] * c[a] - 1.0 / 3.0);
+      e3 += 3.0 * H * rho * ut[a] * ut[a] * ut[b];
+      n3 += 3.0 * H * (2.0 * ut[a] * a2[a][b] + ut[b] * a2[a][a]);
+    }
+    double complex feq = s->w[i] * (rho + 3.0 * rho * cu + 4.5 * e2 + 4.5 * e3);
+    double complex f1 = s->w[i] * (3.0 * (1.0 - d) * cj + 4.5 * n2 + 4.5 * n3);
+    double complex v = feq + (1.0 - 1.0 / tau) * f1;
+    if (force) v += 3.0 * s->w[i] * (c[0] * force[0] + c[1] * force[1] + c[2] * force[2]);
+    out[i] = v;
+  }
+}
+
+static void hrr_collide_s(const stencil_t* s, const double* f, double d, double tau0, double cs,
+                          const double* force, double* out) {
+  double complex fz[QMAX] = {0}, oz[QMAX] = {0};
+  for (int i = 0; i < s->q; ++i) fz[i] = f[i];
+  hrr_collide_z(s, fz, d, tau0, cs, 0, 0.0, force, oz);
+  for (int i = 0; i < s->q; ++i) out[i] = creal(oz[i]);
+}
+
+#define CSTEP 1e-30
+
+/* A[j*q + i] = dC_j/df_i by complex steps f_i + i h (turb FROZEN: tau_frozen). */
+static void hrr_jacobian_s(const stencil_t* s, const double* f, double d, double tau_a, double cs,
+                           int turb, double tau_frozen, double* A) {
+  const int q = s->q;
+  const int freeze = (cs > 0.0 && turb == ORC_TURB_FROZEN);
+  double complex fz[QMAX] = {0}, oz[QMAX] = {0};
+  for (int i = 0; i < q; ++i) {
+    for (int k = 0; k < q; ++k) fz[k] = f[k];
+    fz[i] = CMPLX(f[i], CSTEP);
+    hrr_collide_z(s, fz, d, tau_a, cs, freeze, tau_frozen, NULL, oz);
+    for (int jj = 0; jj < q; ++jj) A[jj * q + i] = cimag(oz[jj]) / CSTEP;
+  }
+}
+
+/* dC_j/dd by a complex step in d (tau_eff does not depend on d). */
+static void hrr_dcdd_s(const stencil_t* s, const double* f, double d, double tau_a, double cs,
+                       int freeze, double tau_frozen, double* out) {
+  double complex fz[QMAX] = {0}, oz[QMAX] = {0};
+  for (int i = 0; i < s->q; ++i) fz[i] = f[i];
+  hrr_collide_z(s, fz, CMPLX(d, CSTEP), tau_a, cs, freeze, tau_frozen, NULL, oz);
+  for (int jj = 0; jj < s->q; ++jj) out[jj] = cimag(oz[jj]) / CSTEP;
+}
+
+void orc_hrr_collide_cell(int stencil, const double* f, double d, double tau0, double cs,
+                          const double* force, double* out) {
+  stencil_t s = get_stencil(stencil);
+  hrr_collide_s(&s, f, d, tau0, cs, force, out);
+}
+
+void orc_hrr_jacobian_cell(int stencil, const double* f, double d, double tau_a, double cs, int turb,
+                           double tau_frozen, double* A) {
+  stencil_t s = get_stencil(stencil);
+  hrr_jacobian_s(&s, f, d, tau_a, cs, turb, tau_frozen, A);
+}
+
+void orc_hrr_dcdd_cell(int stencil, const double* f, double d, double tau_a, double cs, int turb,
+                       double tau_frozen, double* out) {
+  stencil_t s = get_stencil(stencil);
+  hrr_dcdd_s(&s, f, d, tau_a, cs, cs > 0.0 && turb == ORC_TURB_FROZEN, tau_frozen, out);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Objectives (Sec. 4) per cell and their partial derivatives.               */
 /*  FFA  (Eq. obj_ffa):  rho (u_x u0 - u_x^2) + p0 - p,  p = rho/3           */
 /*  DISS (Eq. obj_diss): 2 nu S:S + (nu/K) u.u,  S = -Pi/(2 tau0 cs2),       */
@@ -560,6 +696,7 @@ orc_lattice* orc_create(const orc_params* p) {
   if (p->stencil != ORC_D2Q9 && p->stencil != ORC_D3Q19) return NULL;
   if (p->stencil == ORC_D2Q9 && p->nz != 1) return NULL;
   if (p->bc_y == ORC_BC_INLET_OUTLET || p->bc_z == ORC_BC_INLET_OUTLET) return NULL;
+  if (p->collision != ORC_COLL_BGK && p->collision != ORC_COLL_HRR) return NULL;
   orc_lattice* L = (orc_lattice*)calloc(1, sizeof(orc_lattice));
   L->p = *p;
   if (L->p.stencil == ORC_D2Q9) L->p.bc_z = ORC_BC_PERIODIC;
@@ -700,7 +837,10 @@ static void step_once(orc_lattice* L) {
       inlet_feq(L, c, L->fpost + c * q);
       continue;
     }
-    collide_s(&s, L->f + c * q, L->d[c], L->p.tau, L->p.cs, force, L->fpost + c * q);
+    if (L->p.collision == ORC_COLL_HRR)
+      hrr_collide_s(&s, L->f + c * q, L->d[c], L->p.tau, L->p.cs, force, L->fpost + c * q);
+    else
+      collide_s(&s, L->f + c * q, L->d[c], L->p.tau, L->p.cs, force, L->fpost + c * q);
     if (is_outlet(L, c)) outlet_values_s(&s, L->f + c * q, L->vpost + c * q);
   }
 #pragma omp parallel for schedule(static)
@@ -995,7 +1135,11 @@ int orc_adjoint_prepare(orc_lattice* L, int source, double tau_adj, int turb) {
       fs[i] = (source == 1) ? L->fsum[c * q + i] * inv : L->f[c * q + i];
     double tau_mean = (source == 1) ? L->tau_sum[c] * inv : tau_eff_s(&s, fs, tau0, L->p.cs);
     double tau_frozen = ta + (tau_mean - tau0);
-    jacobian_s(&s, fs, L->d[c], ta, L->p.cs, turb, tau_frozen, A);
+    const int hrr = (L->p.collision == ORC_COLL_HRR);
+    if (hrr)
+      hrr_jacobian_s(&s, fs, L->d[c], ta, L->p.cs, turb, tau_frozen, A);
+    else
+      jacobian_s(&s, fs, L->d[c], ta, L->p.cs, turb, tau_frozen, A);
     if (is_outlet(L, c)) outlet_jacobian_s(&s, fs, L->vjac + c * q * q);
     double tau_used;
     if (L->p.cs == 0.0)
@@ -1004,7 +1148,11 @@ int orc_adjoint_prepare(orc_lattice* L, int source, double tau_adj, int turb) {
       tau_used = tau_eff_s(&s, fs, ta, L->p.cs);
     else
       tau_used = tau_frozen;
-    dcdd_s(&s, fs, L->d[c], tau_used, L->dcdd + c * q);
+    if (hrr)
+      hrr_dcdd_s(&s, fs, L->d[c], ta, L->p.cs, L->p.cs > 0.0 && turb == ORC_TURB_FROZEN, tau_frozen,
+                 L->dcdd + c * q);
+    else
+      dcdd_s(&s, fs, L->d[c], tau_used, L->dcdd + c * q);
     if (mea) { /* a source on the surface cells and their neighbours */
       for (int i = 0; i < q; ++i) L->gsrc[c * q + i] = gmea[c * q + i];
       L->dJdd[c] = 0.0;
@@ -1186,8 +1334,13 @@ int orc_tangent_step(orc_lattice* L, const double* v, long nsteps) {
         for (int i = 0; i < q; ++i) L->tpost[c * q + i] = 0.0;
         continue;
       }
-      jacobian_s(&s, fc, L->d[c], L->p.tau, L->p.cs, ORC_TURB_DIFFERENTIATED, 0.0, A);
-      dcdd_s(&s, fc, L->d[c], tau_eff_s(&s, fc, L->p.tau, L->p.cs), dc);
+      if (L->p.collision == ORC_COLL_HRR) {
+        hrr_jacobian_s(&s, fc, L->d[c], L->p.tau, L->p.cs, ORC_TURB_DIFFERENTIATED, 0.0, A);
+        hrr_dcdd_s(&s, fc, L->d[c], L->p.tau, L->p.cs, 0, 0.0, dc);
+      } else {
+        jacobian_s(&s, fc, L->d[c], L->p.tau, L->p.cs, ORC_TURB_DIFFERENTIATED, 0.0, A);
+        dcdd_s(&s, fc, L->d[c], tau_eff_s(&s, fc, L->p.tau, L->p.cs), dc);
+      }
       for (int jj = 0; jj < q; ++jj) {
         double acc = dc[jj] * v[c];
         for (int i = 0; i < q; ++i) acc += A[jj * q + i] * td[i];

@@ -37,6 +37,7 @@ enum { ORC_INLET_UNIFORM = 1, ORC_INLET_PARABOLIC = 2 };
 enum { ORC_OBJ_FFA = 0, ORC_OBJ_DISS = 1, ORC_OBJ_MOMENTUM = 2, ORC_OBJ_MEA = 3 };
 enum { ORC_TURB_FROZEN = 0, ORC_TURB_DIFFERENTIATED = 1 };
 enum { ORC_NOISE_NONE = 0, ORC_NOISE_RIM = 1, ORC_NOISE_BOX = 2 };
+enum { ORC_COLL_BGK = 0, ORC_COLL_HRR = 1 };
 
 typedef struct {
   int stencil;        /* ORC_D2Q9 or ORC_D3Q19 */
@@ -49,6 +50,7 @@ typedef struct {
   int inlet_profile;  /* ORC_INLET_UNIFORM or ORC_INLET_PARABOLIC (parabolic in y) */
   double u_in;        /* uniform inflow speed, or parabola maximum */
   double force[3];    /* constant body force added after collision (tests only) */
+  int collision;      /* ORC_COLL_BGK (Eq. hlbm) or ORC_COLL_HRR (Eq. HRRLBM) */
 } orc_params;
 
 typedef struct orc_lattice orc_lattice;
@@ -116,6 +118,14 @@ int orc_gradient(const orc_lattice* L, double* g);
  * seed: fdot = 0 at the current state; step: advances f and fdot together;
  * objective: dJ(t)/dd . v of the current objective at the current state. */
 int orc_tangent_seed(orc_lattice* L);
+/* HRRLBM per-cell maps (Eq. HRRLBM): collision, dC/df and dC/dd (complex
+ * steps; turb FROZEN holds tau_frozen). */
+void orc_hrr_collide_cell(int stencil, const double* f, double d, double tau0, double cs,
+                          const double* force, double* out);
+void orc_hrr_jacobian_cell(int stencil, const double* f, double d, double tau_a, double cs, int turb,
+                           double tau_frozen, double* A);
+void orc_hrr_dcdd_cell(int stencil, const double* f, double d, double tau_a, double cs, int turb,
+                       double tau_frozen, double* out);
 int orc_tangent_step(orc_lattice* L, const double* v, long nsteps);
 double orc_tangent_objective(const orc_lattice* L, const double* v);
 int orc_get_tangent(const orc_lattice* L, double* fdot);
