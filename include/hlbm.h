@@ -115,6 +115,16 @@ typedef enum {
   HLBM_FIELD_MEAN_TAU = 5
 } hlbm_field;
 
+/* Collision model.  BGK: the HLBM-BGK collision toward f^eq(rho, d u) (Sec.
+ * 2.1, Eq. hlbm).  HRR: the homogenized recursive regularized collision of
+ * Sec. 2.2 (Eq. HRRLBM): C = f^eq + (1 - 1/tau_eff) f^(1) with the third-
+ * order Hermite equilibrium at (rho, d u) and the regularized non-
+ * equilibrium part (Hermite coefficients a1 = (1 - d) j, a2 projected, a3
+ * recursive from d u and a2), third order restricted to the components
+ * H_aab (a != b) the velocity set supports.  Either takes the Smagorinsky
+ * closure (smagorinsky_cs > 0). */
+typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
+
 typedef struct {
   uint32_t struct_size;   /* sizeof(hlbm_desc) */
   int32_t stencil;        /* hlbm_stencil */
@@ -127,6 +137,7 @@ typedef struct {
   double u_in;            /* uniform inflow speed or parabola maximum */
   double force[3];        /* constant body force 3 w_i xi_i.G added after collision (tests) */
   int32_t track_mean_populations; /* 1: the window also accumulates full mean populations */
+  int32_t collision;      /* hlbm_collision */
   void* stream;           /* hipStream_t or NULL */
 } hlbm_desc;
 

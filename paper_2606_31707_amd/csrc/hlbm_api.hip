@@ -94,6 +94,7 @@ hlbm_status validate_desc(const hlbm_desc* d) {
     if (d->nx < 3) return fail(HLBM_E_INVALID, "inlet/outlet channel needs nx >= 3");
   }
   if (!std::isfinite(d->u_in)) return fail(HLBM_E_INVALID, "u_in not finite");
+  if (d->collision != HLBM_COLL_BGK && d->collision != HLBM_COLL_HRR) return fail(HLBM_E_INVALID, "bad collision");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(d->force[a])) return fail(HLBM_E_INVALID, "force not finite");
   return HLBM_OK;
@@ -621,6 +622,7 @@ hlbm_status hlbm_run_tangent(hlbm_lattice L, const double* v, int64_t n, int32_t
   CHECK_LAT(L);
   if (L->desc.precision != HLBM_FP64) return fail(HLBM_E_INVALID, "the tangent runs on FP64 lattices");
   if (L->desc.smagorinsky_cs > 0.0) return fail(HLBM_E_INVALID, "the tangent has no Smagorinsky closure");
+  if (L->desc.collision != HLBM_COLL_BGK) return fail(HLBM_E_INVALID, "the tangent is written for the BGK collision");
   if (!L->obj_set) return fail(HLBM_E_STATE, "no objective set");
   if (!v || n != L->n) return fail(HLBM_E_INVALID, "v needs %lld values", (long long)L->n);
   if (n_steps < 0 || record_every < 1) return fail(HLBM_E_INVALID, "bad step counts");
@@ -700,6 +702,8 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
     if (L->nsamp == 0 || !L->acc_rho) return fail(HLBM_E_STATE, "mean-flow adjoint needs a non-empty window");
     if (smag && o->turb == HLBM_TURB_DIFFERENTIATED && !L->acc_f)
       return fail(HLBM_E_STATE, "differentiated closure needs track_mean_populations");
+    if (L->desc.collision == HLBM_COLL_HRR && !L->acc_f)
+      return fail(HLBM_E_STATE, "the HRR mean-flow adjoint needs track_mean_populations (mean second moments)");
   }
   const int P = 0;
   (void)P;

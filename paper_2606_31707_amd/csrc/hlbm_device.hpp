@@ -69,6 +69,33 @@ struct Coef {
   static constexpr int NB = 1 + Lat<Q>::D + Lat<Q>::NSYM;  // b0, b1, b2 of dtau/df
 };
 
+// Third-order Hermite components H_aab = xi_b (xi_a^2 - 1/3), a != b, that
+// D2Q9 and D3Q19 support (the third order of the HRRLBM collision).
+template <int Q>
+struct H3Types;
+template <>
+struct H3Types<9> {
+  static constexpr int N = 2;
+  static constexpr int a[2] = {0, 1}, b[2] = {1, 0};
+};
+template <>
+struct H3Types<19> {
+  static constexpr int N = 6;
+  static constexpr int a[6] = {0, 0, 1, 1, 2, 2}, b[6] = {1, 2, 0, 2, 0, 1};
+};
+
+template <int Q>
+__device__ __forceinline__ constexpr int lat_c(int k, int a) {
+  return a == 0 ? Lat<Q>::cx[k] : (a == 1 ? Lat<Q>::cy[k] : Lat<Q>::cz[k]);
+}
+
+// H_aab of direction k for third-order type t.
+template <int Q>
+__device__ __forceinline__ constexpr double h3(int k, int t) {
+  const int ca = lat_c<Q>(k, H3Types<Q>::a[t]), cb = lat_c<Q>(k, H3Types<Q>::b[t]);
+  return cb * (ca * ca - 1.0 / 3.0);
+}
+
 // ---- storage / compute types ----------------------------------------------
 template <typename S>
 struct Prec;

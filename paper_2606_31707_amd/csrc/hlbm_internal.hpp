@@ -93,6 +93,7 @@ struct Coll {
   double tau0, omega0;
   double kS;      // 18 sqrt(2) Cs^2
   int smag;       // closure on
+  int hrr;        // HRRLBM collision (else BGK)
   double force[3];
   int64_t probe_cell;  // cell whose u_y is recorded (-1: none)
   double* probe_out;   // destination of this step's probe value

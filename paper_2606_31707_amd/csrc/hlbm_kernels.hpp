@@ -288,6 +288,75 @@ __device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
   }
 }
 
+// HRRLBM collision (Sec. 2.2, Eq. HRRLBM) on shifted populations s = f - w:
+// s* = (f^eq - w) + (1 - omega) f^(1), f^eq the third-order Hermite
+// equilibrium at (rho, u~ = d u), f^(1) the regularized non-equilibrium part
+// with Hermite coefficients a1 = (1 - d) j, a2 = sum xi xi s - drho/3 I -
+// rho u~u~ (projection) and a3 recursive (a3_aab = 2 u~_a a2_ab + u~_b a2_aa)
+// on the supported third-order components.
+template <int Q, typename T>
+__device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz, T d, T omega,
+                                            const double* force) {
+  using L = Lat<Q>;
+  using H = H3Types<Q>;
+  constexpr int D = L::D;
+  const T rho = (T)1 + drho, ir = (T)1 / rho;
+  const T j[3] = {jx, jy, jz};
+  const T ut[3] = {d * jx * ir, d * jy * ir, d * jz * ir};
+  T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = a; b < D; ++b)
+        if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) S[a][b] += (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * s[k];
+  T a2[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      a2[a][b] = (a < D && b < D) ? S[lo][hi] - (a == b ? drho / (T)3 : (T)0) - rho * ut[a] * ut[b] : (T)0;
+    }
+  const T tt = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const T tr = a2[0][0] + a2[1][1] + a2[2][2];
+  T e3c[H::N], a3[H::N];
+#pragma unroll
+  for (int t = 0; t < H::N; ++t) {
+    const int a = H::a[t], b = H::b[t];
+    e3c[t] = rho * ut[a] * ut[a] * ut[b];
+    a3[t] = (T)2 * ut[a] * a2[a][b] + ut[b] * a2[a][a];
+  }
+  const T omd = (T)1 - d, om1 = (T)1 - omega;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    T cu = 0, cj = 0, n2 = -tr / (T)3, e3 = 0, n3 = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      cu += (T)lat_c<Q>(k, a) * ut[a];
+      cj += (T)lat_c<Q>(k, a) * j[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) n2 += (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * a2[a][b];
+    }
+#pragma unroll
+    for (int t = 0; t < H::N; ++t) {
+      const T h = (T)h3<Q>(k, t);
+      if (h != (T)0) {
+        e3 += h * e3c[t];
+        n3 += h * a3[t];
+      }
+    }
+    const T w = (T)L::w[k];
+    const T feqs = w * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt) + (T)13.5 * e3);
+    const T f1 = w * ((T)3 * omd * cj + (T)4.5 * n2 + (T)13.5 * n3);
+    const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)force[0] + (T)L::cy[k] * (T)force[1] +
+                                        (T)L::cz[k] * (T)force[2]);
+    s[k] = feqs + om1 * f1 + fk;
+  }
+}
+
 // Sweep kernels: 1D grid over the tiles (see sweep_tile).
 #define SWEEP_PROLOGUE                                                       \
   const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x);                \
@@ -400,15 +469,19 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   const bool outlet = inout && (x == g.nx - 1);
   const T uu = ux * ux + uy * uy + uz * uz;
   const T d = (T)dpor[cell];
-  const T tx = d * ux, ty = d * uy, tz = d * uz;
-  const T tt = tx * tx + ty * ty + tz * tz;
+  if (c.hrr) {
+    hrr_collide<Q, T>(s, drho, jx, jy, jz, d, omega, c.force);
+  } else {
+    const T tx = d * ux, ty = d * uy, tz = d * uz;
+    const T tt = tx * tx + ty * ty + tz * tz;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    const T cu = (T)L::cx[k] * tx + (T)L::cy[k] * ty + (T)L::cz[k] * tz;
-    const T feqs = (T)L::w[k] * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt));
-    const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)c.force[0] + (T)L::cy[k] * (T)c.force[1] +
-                                        (T)L::cz[k] * (T)c.force[2]);
-    s[k] = s[k] + omega * (feqs - s[k]) + fk;
+    for (int k = 0; k < Q; ++k) {
+      const T cu = (T)L::cx[k] * tx + (T)L::cy[k] * ty + (T)L::cz[k] * tz;
+      const T feqs = (T)L::w[k] * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt));
+      const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)c.force[0] + (T)L::cy[k] * (T)c.force[1] +
+                                          (T)L::cz[k] * (T)c.force[2]);
+      s[k] = s[k] + omega * (feqs - s[k]) + fk;
+    }
   }
 
   if (!ODD) {
@@ -981,6 +1054,7 @@ struct PrepIn {
   double inv;
   int source;      // 0 steady (current state), 1 window mean
   int smag, turb;  // closure present, 0 frozen / 1 differentiated
+  int hrr;         // HRRLBM collision: its own frozen-coefficient layout
   double tau0, tau_adj, kS;
 };
 
@@ -999,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
   if (!valid || (inout && x == 0)) return;
   double fs[Q];  // shifted populations f - w of the frozen state
   double drho, jx, jy, jz;
-  const bool need_f = (pin.source == 0) || (pin.smag && pin.turb == 1);
+  const bool need_f = (pin.source == 0) || (pin.smag && pin.turb == 1) || pin.hrr;
   if (pin.source == 1) {
     drho = pin.acc_rho[cell] * pin.inv;
     jx = pin.acc_j[cell] * pin.inv;
@@ -1038,6 +1112,41 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
   }
   const double omega = 1.0 / tau_used;
 
+  if (pin.hrr) {
+    // rho, j, d, omega, a2 = sum xi xi (f - w) - drho/3 I - rho u~u~ and, with
+    // the differentiated closure, (1/tau^2) dtau/dPi = cc Pi
+    prep[cell] = (SA)rho;
+    const double jv[3] = {jx, jy, jz};
+    for (int a = 0; a < D; ++a) prep[(1 + a) * g.plane + cell] = (SA)jv[a];
+    prep[(D + 1) * g.plane + cell] = (SA)d;
+    prep[(D + 2) * g.plane + cell] = (SA)omega;
+    double S6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      S6[0] += L::cx[k] * L::cx[k] * fs[k];
+      S6[1] += L::cy[k] * L::cy[k] * fs[k];
+      S6[2] += L::cz[k] * L::cz[k] * fs[k];
+      S6[3] += L::cx[k] * L::cy[k] * fs[k];
+      S6[4] += L::cx[k] * L::cz[k] * fs[k];
+      S6[5] += L::cy[k] * L::cz[k] * fs[k];
+    }
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int m6 = 0; m6 < 6; ++m6) {
+      const int m = sym_index<Q>(m6);
+      if (m < 0) continue;
+      const double a2 = S6[m6] - (m6 < 3 ? drho / 3.0 : 0.0) - rho * ut[ia[m6]] * ut[ib[m6]];
+      prep[(D + 3 + m) * g.plane + cell] = (SA)a2;
+    }
+    if (pin.smag && pin.turb == 1) {
+      const double Pn = sqrt(frob2(P));
+      double cc = 0.0;
+      if (Pn > 0.0) cc = pin.kS / (4.0 * sqrt(ta * ta + pin.kS * Pn) * Pn * tau_used * tau_used);
+      for (int m6 = 0; m6 < 6; ++m6) {
+        const int m = sym_index<Q>(m6);
+        if (m >= 0) prep[(D + 3 + L::NSYM + m) * g.plane + cell] = (SA)(cc * P[m6]);
+      }
+    }
+  } else {
   for (int a = 0; a < D; ++a) prep[a * g.plane + cell] = (SA)ut[a];
   prep[D * g.plane + cell] = (SA)d;
   prep[(D + 1) * g.plane + cell] = (SA)omega;
@@ -1068,6 +1177,7 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
       const int m = sym_index<Q>(m6);
       if (m >= 0) prep[(bo + 1 + D + m) * g.plane + cell] = (SA)(cc * P[m6]);
     }
+  }
   }
   gdat[cell] = rho;
   for (int a = 0; a < D; ++a) gdat[(1 + a) * g.plane + cell] = u[a];
@@ -1106,6 +1216,7 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
 struct AdjC {
   int les;       // per-cell omega
   int diff;      // differentiated closure term
+  int hrr;       // HRRLBM collision (frozen coefficients in the HRR layout)
   double omega0;
 };
 
@@ -1126,6 +1237,216 @@ __device__ __forceinline__ void adjoint_read_canonical(const Geo& g, const SA* _
       if (classify(g, sx, sy, sz) != NB_BOUNCE) ph[k] = (SA)0;
     }
   }
+}
+
+// ---- adjoint of the HRRLBM collision ---------------------------------------
+// The HRR collision depends on f only through rho, j and S = sum xi xi f, so
+// lambda_i = sum_j phi_j dC_j/df_i = G_rho + xi_i.G_j + xi_i xi_i : G_S with
+// G the gradient of Phi = sum_j phi_j C_j(rho, j, S) at the frozen state.
+// In the weighted Hermite moments of phi (m0, m1, M2 = sum w phi H2,
+// M3_t = sum w phi H_t):
+//   Phi = A + (1 - omega) B,
+//   A = rho m0 + 3 d j.m1 + 4.5 rho u~.M2.u~ + 13.5 rho sum_t u~_a^2 u~_b M3_t,
+//   B = 3 (1 - d) j.m1 + 4.5 a2:M2 + 13.5 sum_t a3_t M3_t,
+// differentiated by hand through u~ = d j / rho, a2 = S - rho/3 I - rho u~u~
+// and a3; the differentiated closure adds B (1/tau^2) dtau/dPi : dPi.
+
+// Hermite moments of the canonical adjoint phi_i = ph[opp(i)] (xi_opp(k) = -xi_k).
+template <int Q, typename T>
+__device__ __forceinline__ void hrr_phi_moments(const T (&ph)[Q], T& m0, T (&m1)[3], T (&M2)[3][3],
+                                                T (&M3)[H3Types<Q>::N]) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  m0 = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m1[a] = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M2[a][b] = 0;
+  }
+#pragma unroll
+  for (int t = 0; t < H3Types<Q>::N; ++t) M3[t] = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const T wp = (T)L::w[k] * ph[k];
+    m0 += wp;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (lat_c<Q>(k, a) != 0) m1[a] -= (T)lat_c<Q>(k, a) * wp;
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const T h = (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) - (a == b ? (T)(1.0 / 3.0) : (T)0);
+        if (h != (T)0) M2[a][b] += h * wp;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < H3Types<Q>::N; ++t) {
+      const T h = (T)h3<Q>(k, t);
+      if (h != (T)0) M3[t] -= h * wp;  // H_t is odd in xi
+    }
+  }
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void sym_read(const T* __restrict__ p, int64_t plane, int64_t cell, int base,
+                                         T (&M)[3][3]) {
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[a][b] = 0;
+#pragma unroll
+  for (int m6 = 0; m6 < 6; ++m6) {
+    const int m = sym_index<Q>(m6);
+    if (m < 0) continue;
+    const T v = p[(base + m) * plane + cell];
+    M[ia[m6]][ib[m6]] = v;
+    M[ib[m6]][ia[m6]] = v;
+  }
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void hrr_adjoint(const T (&ph)[Q], const T* __restrict__ prep, int64_t plane,
+                                            int64_t cell, bool diff, T (&lam)[Q]) {
+  using L = Lat<Q>;
+  using H = H3Types<Q>;
+  constexpr int D = L::D;
+  T m0, m1[3], M2[3][3], M3[H::N];
+  hrr_phi_moments<Q, T>(ph, m0, m1, M2, M3);
+  const T rho = prep[cell];
+  T j[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) j[a] = prep[(1 + a) * plane + cell];
+  const T d = prep[(D + 1) * plane + cell];
+  const T omega = prep[(D + 2) * plane + cell];
+  T a2[3][3];
+  sym_read<Q, T>(prep, plane, cell, D + 3, a2);
+  const T ir = (T)1 / rho;
+  const T u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
+  const T ut[3] = {d * u[0], d * u[1], d * u[2]};
+  T M2ut[3], jm1 = 0, utM2ut = 0, trM2 = 0, a2M2 = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    M2ut[a] = M2[a][0] * ut[0] + M2[a][1] * ut[1] + M2[a][2] * ut[2];
+    jm1 += j[a] * m1[a];
+    trM2 += M2[a][a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    utM2ut += ut[a] * M2ut[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) a2M2 += a2[a][b] * M2[a][b];
+  }
+  const T om1 = (T)1 - omega;
+  // A part
+  T Gr = m0 - (T)4.5 * utM2ut;
+  T Gj[3], GS[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Gj[a] = (T)3 * d * m1[a] + (T)9 * d * M2ut[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) GS[a][b] = 0;
+  }
+  // B part (times 1 - omega) and B itself
+  T B = (T)3 * ((T)1 - d) * jm1 + (T)4.5 * a2M2;
+  T GrB = (T)4.5 * (utM2ut - trM2 / (T)3);
+  T GjB[3], GSB[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    GjB[a] = (T)3 * ((T)1 - d) * m1[a] - (T)9 * d * M2ut[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) GSB[a][b] = (T)4.5 * M2[a][b];
+  }
+#pragma unroll
+  for (int t = 0; t < H::N; ++t) {
+    const int a = H::a[t], b = H::b[t];
+    const T m3 = M3[t];
+    const T a3 = (T)2 * ut[a] * a2[a][b] + ut[b] * a2[a][a];
+    Gr -= (T)27 * ut[a] * ut[a] * ut[b] * m3;
+    Gj[a] += (T)27 * d * ut[a] * ut[b] * m3;
+    Gj[b] += (T)13.5 * d * ut[a] * ut[a] * m3;
+    B += (T)13.5 * a3 * m3;
+    GrB += (T)13.5 * m3 * (-a3 * ir + (T)3 * ut[a] * ut[a] * ut[b] - ut[b] / (T)3);
+    GjB[a] += (T)13.5 * m3 * ((T)2 * d * ir * a2[a][b] - (T)4 * d * ut[a] * ut[b]);
+    GjB[b] += (T)13.5 * m3 * (d * ir * a2[a][a] - (T)2 * d * ut[a] * ut[a]);
+    GSB[a][b] += (T)27 * ut[a] * m3;
+    GSB[a][a] += (T)13.5 * ut[b] * m3;
+  }
+  Gr += om1 * GrB;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Gj[a] += om1 * GjB[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) GS[a][b] = om1 * GSB[a][b];
+  }
+  if (diff) {  // omega = 1/tau_eff(Pi), Pi = S - rho/3 I - j j / rho
+    T q[3][3];
+    sym_read<Q, T>(prep, plane, cell, D + 3 + L::NSYM, q);
+    T qu[3], uqu = 0, trq = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qu[a] = q[a][0] * u[0] + q[a][1] * u[1] + q[a][2] * u[2];
+      trq += q[a][a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uqu += u[a] * qu[a];
+    Gr += B * (uqu - trq / (T)3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Gj[a] -= (T)2 * B * qu[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) GS[a][b] += B * q[a][b];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    T v = Gr;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (lat_c<Q>(i, a) == 0) continue;
+      v += (T)lat_c<Q>(i, a) * Gj[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (lat_c<Q>(i, b) != 0) v += (T)(lat_c<Q>(i, a) * lat_c<Q>(i, b)) * GS[a][b];
+    }
+    lam[i] = v;
+  }
+}
+
+// Sum_i phi_i dC_i/dd of the HRRLBM collision at the frozen state (gradient
+// assembly): u~ = d u and a2 depend on d; the closure does not.
+template <int Q>
+__device__ __forceinline__ double hrr_dphi_dd(const double (&ph)[Q], const double* pr, double d) {
+  using H = H3Types<Q>;
+  constexpr int D = Lat<Q>::D;
+  double m0, m1[3], M2[3][3], M3[H::N];
+  hrr_phi_moments<Q, double>(ph, m0, m1, M2, M3);
+  (void)m0;
+  const double rho = pr[0];
+  const double u[3] = {pr[1] / rho, pr[2] / rho, D == 3 ? pr[3] / rho : 0.0};
+  const double omega = pr[D + 2];
+  double a2[3][3];
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) a2[a][b] = 0.0;
+  for (int m6 = 0; m6 < 6; ++m6) {
+    const int m = sym_index<Q>(m6);
+    if (m < 0) continue;
+    a2[ia[m6]][ib[m6]] = a2[ib[m6]][ia[m6]] = pr[D + 3 + m];
+  }
+  double um1 = 0, uM2u = 0;
+  for (int a = 0; a < 3; ++a) {
+    um1 += u[a] * m1[a];
+    for (int b = 0; b < 3; ++b) uM2u += u[a] * M2[a][b] * u[b];
+  }
+  double dA = 3.0 * rho * um1 + 9.0 * d * rho * uM2u;
+  double dB = -3.0 * rho * um1 - 9.0 * d * rho * uM2u;
+  for (int t = 0; t < H::N; ++t) {
+    const int a = H::a[t], b = H::b[t];
+    dA += 40.5 * d * d * rho * u[a] * u[a] * u[b] * M3[t];
+    dB += 13.5 * M3[t] * (2.0 * u[a] * a2[a][b] + u[b] * a2[a][a] - 6.0 * d * d * rho * u[a] * u[a] * u[b]);
+  }
+  return dA + (1.0 - omega) * dB;
 }
 
 template <int Q, typename SA, bool ODD>
@@ -1169,52 +1490,56 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
         ph[k] = A[L::opp[k] * g.plane + cell_of(g, sx, sy, sz)];
     }
   }
-  // weighted moments of phi: m0 = sum w phi, m1 = sum w phi xi, m2 = sum w phi xi xi
-  T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    const T wp = (T)L::w[k] * ph[k];
-    m0 += wp;
-    // phi_i = ph[opp i]; xi_opp(k) = -xi_k
-    m1x -= (T)L::cx[k] * wp;
-    m1y -= (T)L::cy[k] * wp;
-    m1z -= (T)L::cz[k] * wp;
-    mxx += (T)(L::cx[k] * L::cx[k]) * wp;
-    myy += (T)(L::cy[k] * L::cy[k]) * wp;
-    mzz += (T)(L::cz[k] * L::cz[k]) * wp;
-    mxy += (T)(L::cx[k] * L::cy[k]) * wp;
-    mxz += (T)(L::cx[k] * L::cz[k]) * wp;
-    myz += (T)(L::cy[k] * L::cz[k]) * wp;
-  }
-  const T tx = prep[cell];
-  const T ty = prep[g.plane + cell];
-  const T tz = (D == 3) ? prep[2 * g.plane + cell] : (T)0;
-  const T d = prep[D * g.plane + cell];
-  const T omega = ac.les ? prep[(D + 1) * g.plane + cell] : (T)ac.omega0;
-  const T tt = tx * tx + ty * ty + tz * tz;
-  const T m2tx = mxx * tx + mxy * ty + mxz * tz;
-  const T m2ty = mxy * tx + myy * ty + myz * tz;
-  const T m2tz = mxz * tx + myz * ty + mzz * tz;
-  const T tmt = tx * m2tx + ty * m2ty + tz * m2tz;
-  // sum_j phi_j d f^eq_j / d f_i = Phr + Phj . xi_i
-  const T Phr = m0 * ((T)1 + (T)1.5 * tt) - (T)4.5 * tmt;
-  const T Pjx = d * ((T)3 * m1x + (T)9 * m2tx - (T)3 * m0 * tx);
-  const T Pjy = d * ((T)3 * m1y + (T)9 * m2ty - (T)3 * m0 * ty);
-  const T Pjz = d * ((T)3 * m1z + (T)9 * m2tz - (T)3 * m0 * tz);
   T lam[Q];
+  if (ac.hrr) {
+    hrr_adjoint<Q, T>(ph, prep, g.plane, cell, ac.diff != 0, lam);
+  } else {
+    // weighted moments of phi: m0 = sum w phi, m1 = sum w phi xi, m2 = sum w phi xi xi
+    T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    lam[i] = ((T)1 - omega) * ph[L::opp[i]] +
-             omega * (Phr + (T)L::cx[i] * Pjx + (T)L::cy[i] * Pjy + (T)L::cz[i] * Pjz);
-  if (ac.diff) {  // differentiated Smagorinsky: (sum_j phi_j f^neq_j) (1/tau^2) dtau/df_i
-    T sd = 0;
+    for (int k = 0; k < Q; ++k) {
+      const T wp = (T)L::w[k] * ph[k];
+      m0 += wp;
+      // phi_i = ph[opp i]; xi_opp(k) = -xi_k
+      m1x -= (T)L::cx[k] * wp;
+      m1y -= (T)L::cy[k] * wp;
+      m1z -= (T)L::cz[k] * wp;
+      mxx += (T)(L::cx[k] * L::cx[k]) * wp;
+      myy += (T)(L::cy[k] * L::cy[k]) * wp;
+      mzz += (T)(L::cz[k] * L::cz[k]) * wp;
+      mxy += (T)(L::cx[k] * L::cy[k]) * wp;
+      mxz += (T)(L::cx[k] * L::cz[k]) * wp;
+      myz += (T)(L::cy[k] * L::cz[k]) * wp;
+    }
+    const T tx = prep[cell];
+    const T ty = prep[g.plane + cell];
+    const T tz = (D == 3) ? prep[2 * g.plane + cell] : (T)0;
+    const T d = prep[D * g.plane + cell];
+    const T omega = ac.les ? prep[(D + 1) * g.plane + cell] : (T)ac.omega0;
+    const T tt = tx * tx + ty * ty + tz * tz;
+    const T m2tx = mxx * tx + mxy * ty + mxz * tz;
+    const T m2ty = mxy * tx + myy * ty + myz * tz;
+    const T m2tz = mxz * tx + myz * ty + mzz * tz;
+    const T tmt = tx * m2tx + ty * m2ty + tz * m2tz;
+    // sum_j phi_j d f^eq_j / d f_i = Phr + Phj . xi_i
+    const T Phr = m0 * ((T)1 + (T)1.5 * tt) - (T)4.5 * tmt;
+    const T Pjx = d * ((T)3 * m1x + (T)9 * m2tx - (T)3 * m0 * tx);
+    const T Pjy = d * ((T)3 * m1y + (T)9 * m2ty - (T)3 * m0 * ty);
+    const T Pjz = d * ((T)3 * m1z + (T)9 * m2tz - (T)3 * m0 * tz);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) sd += ph[k] * prep[(D + 2 + L::opp[k]) * g.plane + cell];
-    T b[Coef<Q>::NB];
+    for (int i = 0; i < Q; ++i)
+      lam[i] = ((T)1 - omega) * ph[L::opp[i]] +
+               omega * (Phr + (T)L::cx[i] * Pjx + (T)L::cy[i] * Pjy + (T)L::cz[i] * Pjz);
+    if (ac.diff) {  // differentiated Smagorinsky: (sum_j phi_j f^neq_j) (1/tau^2) dtau/df_i
+      T sd = 0;
 #pragma unroll
-    for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = prep[(D + 2 + Q + m) * g.plane + cell];
+      for (int k = 0; k < Q; ++k) sd += ph[k] * prep[(D + 2 + L::opp[k]) * g.plane + cell];
+      T b[Coef<Q>::NB];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lam[i] += sd * quad_eval<Q, T>(b, i);
+      for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = prep[(D + 2 + Q + m) * g.plane + cell];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[i] += sd * quad_eval<Q, T>(b, i);
+    }
   }
   if (outlet) {  // virtual column: sum_j dV_j/df_i phiV_j = (xi_i - u).Psi / rho
     const int64_t o = y + (int64_t)g.ny * z;
@@ -1361,6 +1686,7 @@ __global__ __launch_bounds__(256) void k_gradient(const Geo g, const ObjBox ob, 
                                                   const Dd* __restrict__ dpor,
                                                   const double* __restrict__ gdat,
                                                   const double* __restrict__ src,
+                                                  const SA* __restrict__ prep, int hrr,
                                                   double* __restrict__ out) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -1372,6 +1698,18 @@ __global__ __launch_bounds__(256) void k_gradient(const Geo g, const ObjBox ob, 
   }
   SA ph[Q];
   adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, inout && x == g.nx - 1, ph);
+  if (hrr) {
+    double phd[Q], pr[D + 3 + Lat<Q>::NSYM];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phd[k] = (double)ph[k];
+#pragma unroll
+    for (int m = 0; m < D + 3 + Lat<Q>::NSYM; ++m) pr[m] = (double)prep[m * g.plane + cell];
+    double dJdd = 0.0;
+    int64_t r;
+    if (region_index<Q>(ob, x, y, z, r)) dJdd = src[Coef<Q>::DJDD * ob.rplane + r];
+    out[cell] = dJdd - hrr_dphi_dd<Q>(phd, pr, (double)dpor[cell]);
+    return;
+  }
   double m0 = 0, m1[3] = {0, 0, 0}, m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
   for (int k = 0; k < Q; ++k) {

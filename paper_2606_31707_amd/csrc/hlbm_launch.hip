@@ -57,6 +57,7 @@ Coll make_coll(const hlbm_lattice_s* L) {
   c.omega0 = 1.0 / L->desc.tau;
   c.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
   c.smag = L->desc.smagorinsky_cs > 0.0;
+  c.hrr = L->desc.collision == HLBM_COLL_HRR;
   for (int a = 0; a < 3; ++a) c.force[a] = L->desc.force[a];
   c.probe_cell = -1;
   c.probe_out = nullptr;
@@ -315,6 +316,7 @@ static hipError_t prep_impl(hlbm_lattice_s* L, int source, double tau_adj, int t
   pin.tau0 = L->desc.tau;
   pin.tau_adj = tau_adj;
   pin.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
+  pin.hrr = L->desc.collision == HLBM_COLL_HRR;
   k_adjoint_prep<Q, S, SA><<<cell_grid(L), kBlock, 0, L->stream>>>(
       make_geo(L), make_obj(L), pin, (const S*)L->f, (const S*)L->ghost, L->parity,
       (const typename Prec<S>::Dd*)L->dpor, (SA*)L->prep, L->src, L->gdat, L->oprep);
@@ -330,6 +332,7 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   AdjC ac;
   ac.les = L->adj_les;
   ac.diff = L->adj_diff;
+  ac.hrr = L->desc.collision == HLBM_COLL_HRR;
   ac.omega0 = L->adj_omega;  // used when the relaxation time is uniform (no closure)
   const Geo g = make_geo(L);
   const ObjBox ob = make_obj(L);
@@ -367,7 +370,7 @@ static hipError_t gradient_impl(hlbm_lattice_s* L, double* g_dev) {
   using SA = typename AdjT<S>::type;
   k_gradient<Q, SA, typename Prec<S>::Dd><<<cell_grid(L), kBlock, 0, L->stream>>>(
       make_geo(L), make_obj(L), (const SA*)L->phi, (const typename Prec<S>::Dd*)L->dpor, L->gdat, L->src,
-      g_dev);
+      (const SA*)L->prep, L->desc.collision == HLBM_COLL_HRR, g_dev);
   return hipGetLastError();
 }
 hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev) { HLBM_DISPATCH(L, gradient_impl, L, g_dev); }
@@ -420,6 +423,7 @@ void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out) {
   P->ob = make_obj(L);
   P->ac.les = L->adj_les;
   P->ac.diff = L->adj_diff;
+  P->ac.hrr = L->desc.collision == HLBM_COLL_HRR;
   P->ac.omega0 = L->adj_omega;
   P->A = L->phi;
   P->prep = L->prep;

@@ -25,6 +25,7 @@ TURB_FROZEN, TURB_DIFFERENTIATED = 0, 1
 SOURCE_STEADY, SOURCE_MEAN = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 NOISE_NONE, NOISE_RIM, NOISE_BOX = 0, 1, 2
+COLL_BGK, COLL_HRR = 0, 1
 FIELD_RHO, FIELD_U, FIELD_MEAN_RHO, FIELD_MEAN_U, FIELD_POROSITY, FIELD_MEAN_TAU = range(6)
 
 OK, W_NOT_CONVERGED = 0, 1
@@ -63,6 +64,7 @@ class Desc(C.Structure):
         ("u_in", C.c_double),
         ("force", C.c_double * 3),
         ("track_mean_populations", C.c_int32),
+        ("collision", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -193,7 +195,7 @@ def _out(out, n):
 def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
               bc_x=BC_INLET_OUTLET, bc_y=BC_WALLS, bc_z=BC_PERIODIC,
               inlet_profile=INLET_PARABOLIC, u_in=0.03, force=(0.0, 0.0, 0.0),
-              track_mean_populations=False, stream=None) -> Desc:
+              track_mean_populations=False, collision=0, stream=None) -> Desc:
     d = Desc()
     d.struct_size = C.sizeof(Desc)
     d.stencil, d.precision = stencil, precision
@@ -203,6 +205,7 @@ def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
     d.inlet_profile, d.u_in = inlet_profile, u_in
     d.force = (C.c_double * 3)(*force)
     d.track_mean_populations = int(bool(track_mean_populations))
+    d.collision = int(collision)
     d.stream = stream
     return d
 

@@ -33,6 +33,7 @@ class Spec:
     init_f: np.ndarray | None = None
     obj: tuple | None = None                  # (kind, lo, hi, u0)
     track_mean: bool = False
+    collision: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -43,7 +44,7 @@ class Spec:
 def make_oracle(s: Spec) -> O.Lattice:
     p = O.Params(stencil=s.stencil, nx=s.nx, ny=s.ny, nz=s.nz, tau=s.tau, cs=s.cs, bc_x=s.bc_x,
                  bc_y=s.bc_y, bc_z=s.bc_z, inlet_profile=s.inlet_profile, u_in=s.u_in,
-                 force=tuple(s.force))
+                 force=tuple(s.force), collision=s.collision)
     L = O.Lattice(p)
     if s.porosity is not None:
         L.set_porosity(s.porosity)
@@ -63,7 +64,7 @@ def make_gpu(s: Spec, precision: int = 0):
     from paper_2606_31707_amd import hlbm as H
     G = H.Lattice(stencil=s.stencil, precision=precision, nx=s.nx, ny=s.ny, nz=s.nz, tau=s.tau, cs=s.cs,
                   bc_x=s.bc_x, bc_y=s.bc_y, bc_z=s.bc_z, inlet_profile=s.inlet_profile, u_in=s.u_in,
-                  force=tuple(s.force), track_mean_populations=s.track_mean)
+                  force=tuple(s.force), track_mean_populations=s.track_mean, collision=s.collision)
     if s.porosity is not None:
         G.set_porosity(s.porosity)
     elif s.cyl is not None:
