@@ -319,7 +319,7 @@ def report_serving(n: int, rate: float, cap_gib: float, tick: int, slots: int):
     print(json.dumps(out), flush=True)
 
 
-def report_les(spinup: int, window: int, adj_iters: int, forms):
+def report_les(spinup: int, window: int, adj_iters: int, forms, collision: int = 0):
     """The 3D LES case (768 x 384 x 128 D3Q19, Smagorinsky C_S = 0.1, Re 3900,
     drag plane): FP32, FP16-shifted and FP64 population storage with FP64
     window accumulation; the mean flow of each form against the FP64 form
@@ -339,11 +339,13 @@ def report_les(spinup: int, window: int, adj_iters: int, forms):
 
     for prec in forms:
         name = names[prec]
-        diff = prec == H.FP32  # the differentiated closure needs the full mean populations
+        # the differentiated closure (and every HRR mean-flow adjoint) needs the full mean populations
+        diff = prec == H.FP32
+        track = diff or collision == H.COLL_HRR
         t0 = time.perf_counter()
         G = H.Lattice(stencil=w.stencil, precision=prec, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
                       bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
-                      u_in=w.u_max, track_mean_populations=diff)
+                      u_in=w.u_max, track_mean_populations=track, collision=collision)
         G.build_cylinder(w.xc, w.yc, w.D)
         G.init_equilibrium(1.0, I.initial_velocity(w))
         G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
@@ -415,7 +417,8 @@ def report_les(spinup: int, window: int, adj_iters: int, forms):
         cmp["fp32_fta_vs_diff"] = {"cosine": cos(g[("fp32", "fta")], g[("fp32", "diff")]),
                                    "rel_l2": l2(g[("fp32", "fta")], g[("fp32", "diff")]),
                                    "cosine_tau0.6": cos(g[("fp32", "fta_tau0.6")], g[("fp32", "diff_tau0.6")])}
-    out = {"report": "les", "workload": w.name, "spinup_steps": spinup, "window_steps": window,
+    out = {"report": "les", "workload": w.name, "collision": "hrr" if collision == H.COLL_HRR else "bgk",
+           "spinup_steps": spinup, "window_steps": window,
            "adjoint_max_iters": adj_iters, "forms": res, "comparison": cmp}
     print(json.dumps(out), flush=True)
 
@@ -608,6 +611,7 @@ def main():
     ap.add_argument("--les-window", type=int, default=30000)
     ap.add_argument("--les-adjoint", type=int, default=8000)
     ap.add_argument("--les-forms", default="fp32,fp16s,fp64")
+    ap.add_argument("--les-collision", choices=["bgk", "hrr"], default="bgk")
     ap.add_argument("--v3d-steps", type=int, default=42336)
     ap.add_argument("--v3d-adjoint", type=int, default=60000)
     ap.add_argument("--v3d-fd-scale", type=float, default=1.0 / 3.0)
@@ -635,7 +639,8 @@ def main():
     if args.report == "les":
         forms = {"fp64": H.FP64, "fp32": H.FP32, "fp16s": H.FP16S}
         report_les(args.les_spinup, args.les_window, args.les_adjoint,
-                   [forms[f] for f in args.les_forms.split(",")])
+                   [forms[f] for f in args.les_forms.split(",")],
+                   H.COLL_HRR if args.les_collision == "hrr" else H.COLL_BGK)
         return
     if args.report == "validation3d":
         report_validation3d(args.v3d_steps, args.v3d_adjoint, args.v3d_fd_scale, args.v3d_fd_points)

@@ -316,7 +316,7 @@ void hlbm_destroy(hlbm_lattice L) {
   (void)hipStreamSynchronize(L->stream);
   void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
-                  L->red, L->usnap, L->probe_buf, L->mea_flag, L->tan_f, L->tan_ghost,
+                  L->red, L->usnap, L->probe_buf, L->mea_flag, L->mea_src, L->tan_f, L->tan_ghost,
                   L->tan_v, L->tan_rec};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
@@ -456,6 +456,8 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
     dev_free(L->acc_obj);
     dev_free(L->src);
     dev_free(L->mea_flag);
+    dev_free(L->mea_src);
+    L->mea_src = nullptr;
     L->acc_obj = nullptr;
     L->src = nullptr;
     L->mea_flag = nullptr;
@@ -464,9 +466,16 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
   hlbm_status s;
   if ((s = dev_alloc((void**)&L->acc_obj, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
   if ((s = dev_alloc((void**)&L->src, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
-  if (kind == HLBM_OBJ_MEA && (s = dev_alloc((void**)&L->mea_flag, rp)) != HLBM_OK) return s;
   L->mea_dirty = 1;
   L->rplane = rp > L->rplane ? rp : L->rplane;
+  if (kind == HLBM_OBJ_MEA) {  // sized for the plane stride the kernels index with
+    dev_free(L->mea_flag);
+    dev_free(L->mea_src);
+    L->mea_flag = nullptr;
+    L->mea_src = nullptr;
+    if ((s = dev_alloc((void**)&L->mea_flag, L->rplane)) != HLBM_OK) return s;
+    if ((s = dev_alloc((void**)&L->mea_src, sizeof(double) * L->q * L->rplane)) != HLBM_OK) return s;
+  }
   L->obj_kind = kind;
   for (int a = 0; a < 3; ++a) {
     L->lo[a] = lo[a];
@@ -930,8 +939,9 @@ extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, co
     hlbm_lattice_s* L = lats[i];
     if (!L) return fail(HLBM_E_INVALID, "null member %d", i);
     if (modes[i] < HLBM_GROUP_PRIMAL || modes[i] > HLBM_GROUP_ADJOINT) return fail(HLBM_E_INVALID, "bad mode");
-    if (L->desc.stencil != lats[0]->desc.stencil || L->desc.precision != lats[0]->desc.precision)
-      return fail(HLBM_E_INVALID, "members must share stencil and precision");
+    if (L->desc.stencil != lats[0]->desc.stencil || L->desc.precision != lats[0]->desc.precision ||
+        L->desc.collision != lats[0]->desc.collision)
+      return fail(HLBM_E_INVALID, "members must share stencil, precision and collision model");
     if (modes[i] == HLBM_GROUP_ADJOINT && !L->adj_ready)
       return fail(HLBM_E_STATE, "member %d: adjoint not prepared", i);
     for (int j = 0; j < i; ++j)
@@ -1000,6 +1010,7 @@ extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, co
   g->blocks_adjoint = ba;
   g->stencil = count ? lats[0]->desc.stencil : -1;
   g->precision = count ? lats[0]->desc.precision : -1;
+  g->collision = count ? lats[0]->desc.collision : 0;
   g->steps_since_set = 0;
   return HLBM_OK;
 }
@@ -1010,11 +1021,11 @@ extern "C" hlbm_status hlbm_group_step(hlbm_group g, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const int step = (int)((g->steps_since_set + k) & 1);
     if (g->n_primal > 0)
-      HIP_TRY(launch_primal_packed(g->stream, g->stencil, g->precision, g->tab_primal, g->first_primal, g->n_primal,
-                                   g->blocks_primal, step));
+      HIP_TRY(launch_primal_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_primal,
+                                   g->first_primal, g->n_primal, g->blocks_primal, step));
     if (g->n_adjoint > 0)
-      HIP_TRY(launch_adjoint_packed(g->stream, g->stencil, g->precision, g->tab_adjoint, g->first_adjoint,
-                                    g->n_adjoint, g->blocks_adjoint, step));
+      HIP_TRY(launch_adjoint_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_adjoint,
+                                    g->first_adjoint, g->n_adjoint, g->blocks_adjoint, step));
   }
   for (int i = 0; i < g->count; ++i) {
     hlbm_lattice_s* L = g->members[i];

@@ -39,6 +39,7 @@ struct hlbm_lattice_s {
   int64_t rplane = 0;
   double u0 = 0.0, p0 = 1.0 / 3.0;
   unsigned char* mea_flag = nullptr;  // rplane: J_MEA surface nodes of the region
+  double* mea_src = nullptr;          // q * rplane: J_MEA's constant dJ/df_k over the region
   int mea_dirty = 1;                  // flags to rebuild (porosity or region changed)
 
   // adjoint
@@ -93,7 +94,6 @@ struct Coll {
   double tau0, omega0;
   double kS;      // 18 sqrt(2) Cs^2
   int smag;       // closure on
-  int hrr;        // HRRLBM collision (else BGK)
   double force[3];
   int64_t probe_cell;  // cell whose u_y is recorded (-1: none)
   double* probe_out;   // destination of this step's probe value
@@ -104,7 +104,7 @@ struct ObjBox {
   int lo[3], rn[3];
   int64_t rplane;
   double u0, p0, tau0;           // J_MEA: u0 carries the surface area A
-  const unsigned char* flag;     // J_MEA surface nodes over the region (else null)
+  const double* mea;             // J_MEA: dJ/df_k over the region, plane k (else null)
 };
 
 struct Acc {
@@ -151,17 +151,17 @@ size_t packed_primal_size();
 size_t packed_adjoint_size();
 void fill_packed_primal(const hlbm_lattice_s* L, int accumulate, int first_block, void* out);
 void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out);
-hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
-                                int nm, int blocks, int step);
-hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
-                                 int nm, int blocks, int step);
+hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, int collision, const void* tab,
+                                const int* first, int nm, int blocks, int step);
+hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, int collision, const void* tab,
+                                 const int* first, int nm, int blocks, int step);
 
 }  // namespace hlbm
 
 // A group of lattices stepped by packed launches (see hlbm_group_* in hlbm.h).
 struct hlbm_group_s {
   hipStream_t stream = nullptr;
-  int stencil = -1, precision = -1;
+  int stencil = -1, precision = -1, collision = 0;
   int n_primal = 0, n_adjoint = 0;
   int blocks_primal = 0, blocks_adjoint = 0;
   void* tab_primal = nullptr;   // device tables

@@ -210,16 +210,16 @@ __device__ __forceinline__ bool region_index(const ObjBox& ob, int x, int y, int
 // J = sum_y sum_k g_k(y) f_k(y),  g_k(y) = (xi_k,x / A)(s(y) + s(y - xi_k)),
 // with s the surface flag (0 unless y - xi_k is a lattice cell of the
 // region).  g is the constant adjoint source; dJ/dd = 0.
+// g is tabulated per region cell when the flags change (k_mea_source).
 template <int Q>
 __device__ __forceinline__ double mea_g(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
                                         int k) {
-  using L = Lat<Q>;
-  if (L::cx[k] == 0) return 0.0;
-  double s = (double)ob.flag[r];
-  int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
-  int64_t rr;
-  if (classify(g, sx, sy, sz) == NB_CELL && region_index<Q>(ob, sx, sy, sz, rr)) s += (double)ob.flag[rr];
-  return (double)L::cx[k] / ob.u0 * s;
+  (void)g;
+  (void)x;
+  (void)y;
+  (void)z;
+  if (Lat<Q>::cx[k] == 0) return 0.0;
+  return ob.mea[k * ob.rplane + r];
 }
 
 // Region-cell terms of J_MEA from the shifted state sd (only J is nonzero).
@@ -387,7 +387,10 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
 // =========================================================================
 
 // One lattice update of cell (x, y, z) (inside the lattice).
-template <int Q, typename S, bool ODD, bool ACC>
+// ACC: 0 no window; 1 window with the moment-form objective terms; 2 window
+// with J_MEA (its own terms; a separate instantiation keeps the register
+// budget of the common case).
+template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
                                             const typename Prec<S>::Dd* __restrict__ dpor,
                                             S* __restrict__ ghost, const Acc& acc, const int x, const int y,
@@ -437,7 +440,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     omega = (T)1 / taue;
   }
 
-  if (ACC) {
+  if constexpr (ACC != 0) {
     acc.rho[cell] += (double)drho;
     acc.j[cell] += (double)jx;
     acc.j[g.plane + cell] += (double)jy;
@@ -453,7 +456,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
       double terms[Coef<Q>::N];
-      if (ob.kind == OBJ_MEA) {
+      if constexpr (ACC == 2) {
         mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
       } else {
         double dr, ax, ay, az, P[6];
@@ -469,7 +472,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   const bool outlet = inout && (x == g.nx - 1);
   const T uu = ux * ux + uy * uy + uz * uz;
   const T d = (T)dpor[cell];
-  if (c.hrr) {
+  if constexpr (HRR) {
     hrr_collide<Q, T>(s, drho, jx, jy, jz, d, omega, c.force);
   } else {
     const T tx = d * ux, ty = d * uy, tz = d * uz;
@@ -516,14 +519,14 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
 }
 
-template <int Q, typename S, bool ODD, bool ACC>
+template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const ObjBox ob,
                                                 S* __restrict__ A,
                                                 const typename Prec<S>::Dd* __restrict__ dpor,
                                                 S* __restrict__ ghost, const Acc acc) {
   SWEEP_PROLOGUE
   if (!valid) return;
-  primal_cell<Q, S, ODD, ACC>(g, c, ob, A, dpor, ghost, acc, x, y, z);
+  primal_cell<Q, S, ODD, ACC, HRR>(g, c, ob, A, dpor, ghost, acc, x, y, z);
 }
 
 // =========================================================================
@@ -734,7 +737,7 @@ __device__ __forceinline__ int packed_member(const int* __restrict__ first, int 
   return m;
 }
 
-template <int Q, typename S>
+template <int Q, typename S, bool HRR>
 __global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __restrict__ tab,
                                                        const int* __restrict__ first, int nm, int step) {
   using Dd = typename Prec<S>::Dd;
@@ -748,16 +751,21 @@ __global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __res
   S* A = (S*)P.A;
   const Dd* dp = (const Dd*)P.dpor;
   S* gh = (S*)P.ghost;
+  const int mode = P.accumulate ? (P.ob.kind == OBJ_MEA ? 2 : 1) : 0;
   if ((P.parity0 + step) & 1) {
-    if (P.accumulate)
-      primal_cell<Q, S, true, true>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    if (mode == 1)
+      primal_cell<Q, S, true, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    else if (mode == 2)
+      primal_cell<Q, S, true, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
     else
-      primal_cell<Q, S, true, false>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, true, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
   } else {
-    if (P.accumulate)
-      primal_cell<Q, S, false, true>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    if (mode == 1)
+      primal_cell<Q, S, false, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+    else if (mode == 2)
+      primal_cell<Q, S, false, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
     else
-      primal_cell<Q, S, false, false>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, false, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
   }
 }
 
@@ -818,6 +826,26 @@ __global__ __launch_bounds__(256) void k_mea_flags(const Geo g, const ObjBox ob,
     }
   }
   flag[r] = s;
+}
+
+// g_k(y) = (xi_k,x / A)(s(y) + s(y - xi_k)) from the surface flags.
+template <int Q>
+__global__ __launch_bounds__(256) void k_mea_source(const Geo g, const ObjBox ob,
+                                                    const unsigned char* __restrict__ flag,
+                                                    double* __restrict__ mea) {
+  using L = Lat<Q>;
+  CELL_PROLOGUE
+  if (!valid) return;
+  int64_t r;
+  if (!region_index<Q>(ob, x, y, z, r)) return;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double s = (double)flag[r];
+    int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+    int64_t rr;
+    if (classify(g, sx, sy, sz) == NB_CELL && region_index<Q>(ob, sx, sy, sz, rr)) s += (double)flag[rr];
+    mea[k * ob.rplane + r] = (double)L::cx[k] / ob.u0 * s;
+  }
 }
 
 template <typename Dd>
@@ -1216,7 +1244,6 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(const Geo g, const ObjBox 
 struct AdjC {
   int les;       // per-cell omega
   int diff;      // differentiated closure term
-  int hrr;       // HRRLBM collision (frozen coefficients in the HRR layout)
   double omega0;
 };
 
@@ -1449,7 +1476,7 @@ __device__ __forceinline__ double hrr_dphi_dd(const double (&ph)[Q], const doubl
   return dA + (1.0 - omega) * dB;
 }
 
-template <int Q, typename SA, bool ODD>
+template <int Q, typename SA, bool ODD, bool HRR, bool MEA>
 __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, const AdjC& ac, SA* __restrict__ A,
                                              const SA* __restrict__ prep, const double* __restrict__ src,
                                              const double* __restrict__ oprep, const SA* __restrict__ pv_in,
@@ -1491,7 +1518,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     }
   }
   T lam[Q];
-  if (ac.hrr) {
+  if constexpr (HRR) {
     hrr_adjoint<Q, T>(ph, prep, g.plane, cell, ac.diff != 0, lam);
   } else {
     // weighted moments of phi: m0 = sum w phi, m1 = sum w phi xi, m2 = sum w phi xi xi
@@ -1578,7 +1605,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     for (int m = 0; m < 1 + D + L::NSYM; ++m) a[m] = (T)src[(Coef<Q>::A0 + m) * ob.rplane + r];
 #pragma unroll
     for (int i = 0; i < Q; ++i) lam[i] -= quad_eval<Q, T>(a, i);
-    if (ob.kind == OBJ_MEA) {
+    if constexpr (MEA) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) lam[i] -= (T)mea_g<Q>(g, ob, x, y, z, r, i);
     }
@@ -1605,7 +1632,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   }
 }
 
-template <int Q, typename SA, bool ODD>
+template <int Q, typename SA, bool ODD, bool HRR, bool MEA>
 __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, const AdjC ac,
                                                  SA* __restrict__ A, const SA* __restrict__ prep,
                                                  const double* __restrict__ src,
@@ -1613,7 +1640,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
                                                  const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
   SWEEP_PROLOGUE
   if (!valid) return;
-  adjoint_cell<Q, SA, ODD>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z);
+  adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z);
 }
 
 struct PackedAdjoint {
@@ -1630,7 +1657,7 @@ struct PackedAdjoint {
   int first_block, tiles_x, tiles_y, pad_;
 };
 
-template <int Q, typename SA>
+template <int Q, typename SA, bool HRR>
 __global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __restrict__ tab,
                                                         const int* __restrict__ first, int nm, int step) {
   const int b = sweep_tile((int)blockIdx.x, (int)gridDim.x);
@@ -1643,10 +1670,20 @@ __global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __r
   const int cur = (P.pvcur0 + step) & 1;
   const SA* pin = (const SA*)P.pv[cur];
   SA* pout = (SA*)P.pv[cur ^ 1];
-  if ((P.iter0 + step) & 1)
-    adjoint_cell<Q, SA, true>(P.g, P.ob, P.ac, (SA*)P.A, (const SA*)P.prep, P.src, P.oprep, pin, pout, x, y, z);
-  else
-    adjoint_cell<Q, SA, false>(P.g, P.ob, P.ac, (SA*)P.A, (const SA*)P.prep, P.src, P.oprep, pin, pout, x, y, z);
+  SA* A = (SA*)P.A;
+  const SA* pr = (const SA*)P.prep;
+  const bool odd = ((P.iter0 + step) & 1) != 0;
+  if (P.ob.kind == OBJ_MEA) {
+    if (odd)
+      adjoint_cell<Q, SA, true, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+    else
+      adjoint_cell<Q, SA, false, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+  } else {
+    if (odd)
+      adjoint_cell<Q, SA, true, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+    else
+      adjoint_cell<Q, SA, false, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+  }
 }
 
 // Residual: max |phi - snapshot| and max |phi| over the state cells.

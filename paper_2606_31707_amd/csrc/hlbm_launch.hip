@@ -47,7 +47,7 @@ ObjBox make_obj(const hlbm_lattice_s* L) {
   o.u0 = L->u0;
   o.p0 = L->p0;
   o.tau0 = L->desc.tau;
-  o.flag = L->mea_flag;
+  o.mea = L->mea_src;
   return o;
 }
 
@@ -57,7 +57,6 @@ Coll make_coll(const hlbm_lattice_s* L) {
   c.omega0 = 1.0 / L->desc.tau;
   c.kS = 18.0 * sqrt(2.0) * L->desc.smagorinsky_cs * L->desc.smagorinsky_cs;
   c.smag = L->desc.smagorinsky_cs > 0.0;
-  c.hrr = L->desc.collision == HLBM_COLL_HRR;
   for (int a = 0; a < 3; ++a) c.force[a] = L->desc.force[a];
   c.probe_cell = -1;
   c.probe_out = nullptr;
@@ -80,8 +79,11 @@ static dim3 sweep_grid(const hlbm_lattice_s* L) {
   return dim3(c.x * c.y * c.z, 1, 1);
 }
 
-template <int Q, typename S>
-static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+// The collision model is a template parameter: the HRR collision needs far
+// more registers, which would lower the occupancy of the BGK sweeps if both
+// shared one kernel.
+template <int Q, typename S, int ACC, bool HRR>
+static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
   using Dd = typename Prec<S>::Dd;
   const Geo g = make_geo(L);
   const Coll c = make_coll(L);
@@ -92,17 +94,28 @@ static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, 
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
   const dim3 grid = sweep_grid(L);
-  if (L->parity == 0) {
-    if (accumulate)
-      launch_k(k_primal<Q, S, false, true>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
-    else
-      launch_k(k_primal<Q, S, false, false>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
-  } else {
-    if (accumulate)
-      launch_k(k_primal<Q, S, true, true>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
-    else
-      launch_k(k_primal<Q, S, true, false>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
-  }
+  if (L->parity == 0)
+    launch_k(k_primal<Q, S, false, ACC, HRR>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+  else
+    launch_k(k_primal<Q, S, true, ACC, HRR>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+}
+
+template <int Q, typename S, bool HRR>
+static void primal_mode(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+  if (!accumulate)
+    primal_variant<Q, S, 0, HRR>(L, e0, e1);
+  else if (L->obj_set && L->obj_kind == HLBM_OBJ_MEA)
+    primal_variant<Q, S, 2, HRR>(L, e0, e1);
+  else
+    primal_variant<Q, S, 1, HRR>(L, e0, e1);
+}
+
+template <int Q, typename S>
+static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+  if (L->desc.collision == HLBM_COLL_HRR)
+    primal_mode<Q, S, true>(L, accumulate, e0, e1);
+  else
+    primal_mode<Q, S, false>(L, accumulate, e0, e1);
   return hipGetLastError();
 }
 
@@ -156,11 +169,13 @@ hipError_t launch_mea_flags(hlbm_lattice_s* L) {
       k_mea_flags<9, double><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const double*)L->dpor, fl);
     else
       k_mea_flags<9, float><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const float*)L->dpor, fl);
+    k_mea_source<9><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, fl, L->mea_src);
   } else {
     if (f64)
       k_mea_flags<19, double><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const double*)L->dpor, fl);
     else
       k_mea_flags<19, float><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, (const float*)L->dpor, fl);
+    k_mea_source<19><<<cell_grid(L), kBlock, 0, L->stream>>>(g, ob, fl, L->mea_src);
   }
   return hipGetLastError();
 }
@@ -332,7 +347,6 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   AdjC ac;
   ac.les = L->adj_les;
   ac.diff = L->adj_diff;
-  ac.hrr = L->desc.collision == HLBM_COLL_HRR;
   ac.omega0 = L->adj_omega;  // used when the relaxation time is uniform (no closure)
   const Geo g = make_geo(L);
   const ObjBox ob = make_obj(L);
@@ -340,12 +354,26 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   const SA* pin = (const SA*)L->pv[L->pvcur];
   SA* pout = (SA*)L->pv[L->pvcur ^ 1];
   const SA* prep = (const SA*)L->prep;
-  if ((L->adj_iters & 1) == 0)
-    launch_k(k_adjoint<Q, SA, false>, sweep_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
-             L->oprep, pin, pout);
-  else
-    launch_k(k_adjoint<Q, SA, true>, sweep_grid(L), kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src,
-             L->oprep, pin, pout);
+  const bool odd = (L->adj_iters & 1) != 0;
+  const bool hrr = L->desc.collision == HLBM_COLL_HRR, mea = L->obj_kind == HLBM_OBJ_MEA;
+  const dim3 grid = sweep_grid(L);
+#define HLBM_ADJ(ODD, HRR, MEA)                                                                        \
+  launch_k(k_adjoint<Q, SA, ODD, HRR, MEA>, grid, kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src, \
+           L->oprep, pin, pout)
+  if (hrr) {
+    if (mea) {
+      if (odd) HLBM_ADJ(true, true, true); else HLBM_ADJ(false, true, true);
+    } else {
+      if (odd) HLBM_ADJ(true, true, false); else HLBM_ADJ(false, true, false);
+    }
+  } else {
+    if (mea) {
+      if (odd) HLBM_ADJ(true, false, true); else HLBM_ADJ(false, false, true);
+    } else {
+      if (odd) HLBM_ADJ(true, false, false); else HLBM_ADJ(false, false, false);
+    }
+  }
+#undef HLBM_ADJ
   return hipGetLastError();
 }
 hipError_t launch_adjoint_step(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
@@ -423,7 +451,6 @@ void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out) {
   P->ob = make_obj(L);
   P->ac.les = L->adj_les;
   P->ac.diff = L->adj_diff;
-  P->ac.hrr = L->desc.collision == HLBM_COLL_HRR;
   P->ac.omega0 = L->adj_omega;
   P->A = L->phi;
   P->prep = L->prep;
@@ -442,37 +469,56 @@ void fill_packed_adjoint(const hlbm_lattice_s* L, int first_block, void* out) {
 size_t packed_primal_size() { return sizeof(PackedPrimal); }
 size_t packed_adjoint_size() { return sizeof(PackedAdjoint); }
 
-hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
-                                int nm, int blocks, int step) {
+template <int Q, typename S>
+static void primal_packed(hipStream_t st, bool hrr, const PackedPrimal* t, const int* first, int nm, int blocks,
+                          int step) {
   const dim3 grid((unsigned)blocks);
+  if (hrr)
+    k_primal_packed<Q, S, true><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+  else
+    k_primal_packed<Q, S, false><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+}
+
+hipError_t launch_primal_packed(hipStream_t st, int stencil, int precision, int collision, const void* tab,
+                                const int* first, int nm, int blocks, int step) {
   const PackedPrimal* t = (const PackedPrimal*)tab;
+  const bool hrr = collision == HLBM_COLL_HRR;
   switch (stencil * 3 + precision) {
-    case 0: k_primal_packed<9, double><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
-    case 1: k_primal_packed<9, float><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
-    case 2: k_primal_packed<9, _Float16><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
-    case 3: k_primal_packed<19, double><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
-    case 4: k_primal_packed<19, float><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
-    case 5: k_primal_packed<19, _Float16><<<grid, kBlock, 0, st>>>(t, first, nm, step); break;
+    case 0: primal_packed<9, double>(st, hrr, t, first, nm, blocks, step); break;
+    case 1: primal_packed<9, float>(st, hrr, t, first, nm, blocks, step); break;
+    case 2: primal_packed<9, _Float16>(st, hrr, t, first, nm, blocks, step); break;
+    case 3: primal_packed<19, double>(st, hrr, t, first, nm, blocks, step); break;
+    case 4: primal_packed<19, float>(st, hrr, t, first, nm, blocks, step); break;
+    case 5: primal_packed<19, _Float16>(st, hrr, t, first, nm, blocks, step); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, const void* tab, const int* first,
-                                 int nm, int blocks, int step) {
+template <int Q, typename SA>
+static void adjoint_packed(hipStream_t st, bool hrr, const PackedAdjoint* t, const int* first, int nm, int blocks,
+                           int step) {
   const dim3 grid((unsigned)blocks);
+  if (hrr)
+    k_adjoint_packed<Q, SA, true><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+  else
+    k_adjoint_packed<Q, SA, false><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+}
+
+hipError_t launch_adjoint_packed(hipStream_t st, int stencil, int precision, int collision, const void* tab,
+                                 const int* first, int nm, int blocks, int step) {
   const PackedAdjoint* t = (const PackedAdjoint*)tab;
-  const bool f64 = precision == HLBM_FP64;
+  const bool f64 = precision == HLBM_FP64, hrr = collision == HLBM_COLL_HRR;
   if (stencil == HLBM_D2Q9) {
     if (f64)
-      k_adjoint_packed<9, double><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+      adjoint_packed<9, double>(st, hrr, t, first, nm, blocks, step);
     else
-      k_adjoint_packed<9, float><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+      adjoint_packed<9, float>(st, hrr, t, first, nm, blocks, step);
   } else {
     if (f64)
-      k_adjoint_packed<19, double><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+      adjoint_packed<19, double>(st, hrr, t, first, nm, blocks, step);
     else
-      k_adjoint_packed<19, float><<<grid, kBlock, 0, st>>>(t, first, nm, step);
+      adjoint_packed<19, float>(st, hrr, t, first, nm, blocks, step);
   }
   return hipGetLastError();
 }
