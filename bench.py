@@ -146,8 +146,7 @@ def traffic_for(kernel_hash: str):
 
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv -- "
-             "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 20000 "
-             "--adjoint-max 6000",
+             "python3 bench.py",
     "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/FETCH_SIZE -o bench --output-format csv -- "
                   "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 400 "
                   "--adjoint-max 100 --profile-every 0",
@@ -159,8 +158,8 @@ PROFILE_CMDS = {
     "copy_WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_WRITE_SIZE -o copy --output-format csv "
                        "-- python3 bench.py --copy-calibration-mib 512",
 }
-PRIMAL_EVEN = "hlbm::k_primal<9, double, false, false>"
-PRIMAL_ODD = "hlbm::k_primal<9, double, true, false>"
+PRIMAL_EVEN = "hlbm::k_primal<9, double, false, 0, false>"
+PRIMAL_ODD = "hlbm::k_primal<9, double, true, 0, false>"
 
 
 def summarize_profiles(d: str):
@@ -184,16 +183,26 @@ def summarize_profiles(d: str):
     lines = ["# Kernel trace: vortex_re100 (1100x410, D2Q9, FP64) gradient query", "",
              "Command (run from the repository root on the MI355X box, `export TMPDIR=/tmp`):", "", "```",
              PROFILE_CMDS["trace"], "```", "",
-             "Same query as the benchmark with 20 000 primal steps (window = last 20 %) and 6 000 adjoint "
-             "iterations, so the trace stays small; per-launch durations do not depend on the step count.", "",
+             "The benchmark command itself (warm-up query, three timed FP64 queries, the FP32 query and the "
+             "CPU-oracle sample); the FP32 kernels appear under their own names.", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     alg = 152 * w.n
-    lines += ["", f"Dominant kernel `k_primal<9,double,*,false>`: mean of the even and odd AA steps = "
+    live = None
+    try:
+        for line in open(os.path.join(d, "trace.log")):
+            if line.startswith("{") and '"roofline"' in line:
+                live = json.loads(line)["roofline"]
+    except OSError:
+        pass
+    lines += ["", f"Dominant kernel `k_primal<9,double,*,0,false>`: mean of the even and odd AA steps = "
                   f"{mean_us:.2f} us per launch; 152 algorithmic B/LU x {w.n} cells / that duration = "
                   f"{alg / mean_us / 1e3:.0f} GB/s ({alg / mean_us / 1e3 / HBM_PEAK_GBS * 100:.1f} % of 8 TB/s)."]
+    if live:
+        lines += [f"The same run's live figure (HIP events at kernel start/end, one launch in 49 sampled, "
+                  f"inside bench.py): {live['us_per_launch']:.2f} us per launch, {live['achieved']:.0f} GB/s."]
 
     def per_launch(sub, counter):
         vals = {PRIMAL_EVEN: [], PRIMAL_ODD: []}
@@ -214,7 +223,7 @@ def summarize_profiles(d: str):
     rd = 0.5 * (fetch["even"] + fetch["odd"]) * ff * 1024
     wr = 0.5 * (write["even"] + write["odd"]) * wf * 1024
     rec = {
-        "kernel": "k_primal<9, double, *, false> (AA even + odd, no window), 1100x410 vortex_re100",
+        "kernel": "k_primal<9, double, *, 0, false> (AA even + odd, no window, BGK), 1100x410 vortex_re100",
         "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
         "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 512 MiB)", "fetch_kib": cf,
                         "write_kib": cw, "fetch_factor": ff, "write_factor": wf},
