@@ -190,19 +190,19 @@ def summarize_profiles(d: str):
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     alg = 152 * w.n
-    live = None
+    live = None  # an unprofiled run of the same command (the profiler slows the sampled launches)
     try:
-        for line in open(os.path.join(d, "trace.log")):
-            if line.startswith("{") and '"roofline"' in line:
-                live = json.loads(line)["roofline"]
-    except OSError:
+        live = json.load(open(os.path.join(d, "bench.json")))["roofline"]
+    except (OSError, ValueError, KeyError):
         pass
     lines += ["", f"Dominant kernel `k_primal<9,double,*,0,false>`: mean of the even and odd AA steps = "
                   f"{mean_us:.2f} us per launch; 152 algorithmic B/LU x {w.n} cells / that duration = "
                   f"{alg / mean_us / 1e3:.0f} GB/s ({alg / mean_us / 1e3 / HBM_PEAK_GBS * 100:.1f} % of 8 TB/s)."]
     if live:
-        lines += [f"The same run's live figure (HIP events at kernel start/end, one launch in 49 sampled, "
-                  f"inside bench.py): {live['us_per_launch']:.2f} us per launch, {live['achieved']:.0f} GB/s."]
+        lines += [f"The benchmark's own figure for this kernel in an unprofiled run of the same command on the "
+                  f"same box (HIP events recorded at kernel start and end, one launch in 49 sampled): "
+                  f"{live['us_per_launch']:.2f} us per launch, {live['achieved']:.0f} GB/s (the event pair "
+                  f"around a sampled launch adds a fraction of a microsecond)."]
 
     def per_launch(sub, counter):
         vals = {PRIMAL_EVEN: [], PRIMAL_ODD: []}
