@@ -883,10 +883,17 @@ extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, dou
   if (smag) pw += 16.0;
   pw += rfrac * 16.0 * L->ncoef;
   // adjoint: read + write phi, read the frozen coefficients and the source
-  double a = 2.0 * q * as + as * (dim + 1.0);
-  if (smag) a += as;
-  if (L->adj_diff) a += as * (q + L->nb);
-  a += rfrac * 8.0 * (L->ncoef - 2);
+  const double nsym = dim == 2 ? 3.0 : 6.0;
+  double a = 2.0 * q * as;
+  if (L->desc.collision == HLBM_COLL_HRR) {
+    a += as * (dim + 3.0 + nsym);  // rho, j, d, omega, a2
+    if (L->adj_diff) a += as * nsym;
+  } else {
+    a += as * (dim + 1.0);  // u~, d
+    if (smag) a += as;      // omega per cell
+    if (L->adj_diff) a += as * (q + L->nb);
+  }
+  a += rfrac * 8.0 * (L->obj_kind == HLBM_OBJ_MEA ? q : L->ncoef - 2);
   if (primal) *primal = p;
   if (primal_window) *primal_window = pw;
   if (adjoint) *adjoint = a;
