@@ -359,7 +359,7 @@ def report_les(spinup: int, window: int, adj_iters: int, forms, collision: int =
         G.init_equilibrium(1.0, I.initial_velocity(w))
         G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
         G.profile_enable(97)
-        r = {"track_mean_populations": diff}
+        r = {"track_mean_populations": track}
         ok = True
         for done in range(0, spinup, chunk):
             G.run_primal(min(chunk, spinup - done))
@@ -630,7 +630,7 @@ def main():
     ap.add_argument("--tan-record", type=int, default=50)
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--rate", type=float, default=2.0)
-    ap.add_argument("--mem-cap-gib", type=float, default=16.0)
+    ap.add_argument("--mem-cap-gib", type=float, default=1.0)
     ap.add_argument("--tick", type=int, default=256)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
