@@ -5,13 +5,15 @@
  * of Ito et al., "Mean-Flow Adjoint Sensitivity Analysis of Unsteady Flow
  * Around Porous Cylinders Using a Homogenized Lattice Boltzmann Method":
  *
- *   primal HLBM sweep (Sec. 2, Eq. hlbm; optional Smagorinsky closure,
- *   Eqs. sgsStress/turbVisc/tauEff)  ->  FP64 tracking average of the flow
- *   (Sec. 3.3, Eq. averageObjective)  ->  adjoint LBM sweep on the frozen
- *   (mean) flow (Sec. 3.2-3.3, Eqs. adjoint_steady/adjoint_unsteady)  ->
- *   gradient assembly dJ/dd over the porosity field (Eqs. gradients_steady/
- *   gradients_unsteady), for the drag (J_FFA, Eq. obj_ffa) and dissipation
- *   (J_DISS, Eq. obj_diss) objectives (Sec. 4).
+ *   primal HLBM sweep (Sec. 2, Eq. hlbm, or the HRRLBM collision of Eq.
+ *   HRRLBM; optional Smagorinsky closure, Eqs. sgsStress/turbVisc/tauEff)
+ *   ->  FP64 tracking average of the flow (Sec. 3.3, Eq. averageObjective)
+ *   ->  adjoint LBM sweep on the frozen (mean) flow (Sec. 3.2-3.3, Eqs.
+ *   adjoint_steady/adjoint_unsteady)  ->  gradient assembly dJ/dd over the
+ *   porosity field (Eqs. gradients_steady/gradients_unsteady), for the drag
+ *   (J_FFA, Eq. obj_ffa; J_MEA, Eq. obj_mea) and dissipation (J_DISS, Eq.
+ *   obj_diss) objectives (Sec. 4); and the forward tangent of the transient
+ *   (App. C).
  *
  * The call sequence follows the paper's problem statement (Sec. 3.1: minimise
  * J(alpha, f) subject to the lattice Boltzmann residual G(alpha, f) = 0, and
@@ -248,7 +250,9 @@ hlbm_status hlbm_run_tangent(hlbm_lattice lat, const double* v, int64_t n, int32
 
 /* Freeze the Jacobian data (row a7) and iterate the adjoint sweep (row a8).
  * Returns STATE without an objective (or without a window for MEAN, or
- * without tracked mean populations for the differentiated closure). */
+ * without tracked mean populations for the differentiated closure or for a
+ * MEAN source with the HRR collision, whose frozen data include the mean
+ * second moments). */
 hlbm_status hlbm_solve_adjoint(hlbm_lattice lat, const hlbm_adjoint_opts* opts,
                                hlbm_adjoint_report* report);
 /* dJ/dd[n] (FP64), 0 on the inlet column (row a9). */
@@ -303,7 +307,7 @@ hlbm_status hlbm_group_create(void* stream, hlbm_group* out);
 void hlbm_group_destroy(hlbm_group g);
 /* Sets the members (the lattices stay owned by the caller) and what each does
  * per step.  Synchronises every member's own stream.  Members must share
- * stencil and precision; ADJOINT members need a prepared adjoint
+ * stencil, precision and collision model; ADJOINT members need a prepared adjoint
  * (hlbm_solve_adjoint with max_iters = 0).  Until the next hlbm_group_set the
  * members may not be advanced by any other call.  count = 0 empties it. */
 hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, const int32_t* modes, int32_t count);

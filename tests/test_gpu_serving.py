@@ -59,6 +59,51 @@ def test_group_steps_equal_individual_launches(prec):
         assert _same(a.gradient(), b.gradient(), prec)
 
 
+def test_group_hrr_and_mea_members_equal_individual_launches():
+    """Packed launches of HRRLBM members (the collision is a template
+    parameter of the packed kernels too) with a J_MEA and a J_DISS member:
+    bitwise equal to the members' own launches."""
+    from paper_2606_31707_amd import hlbm as H
+    say("group hrr + mea")
+
+    def lat(nx, ny, seed, kind):
+        G = H.Lattice(stencil=H.D2Q9, precision=H.FP32, nx=nx, ny=ny, tau=0.58, u_in=0.05, collision=H.COLL_HRR,
+                      track_mean_populations=True)
+        G.build_cylinder(nx / 4, (ny - 1) / 2, ny / 4)
+        G.init_equilibrium()
+        if kind == H.OBJ_MEA:
+            G.set_objective(kind, (2, 0, 0), (nx // 2, ny - 1, 0), u0=np.pi * ny / 4)
+        else:
+            G.set_objective(kind, (2, 0, 0), (nx - 3, ny - 1, 0))
+        return G
+
+    spec = [(120, 60, 0, H.OBJ_MEA), (96, 44, 1, H.OBJ_DISS)]
+    solo = [lat(*a) for a in spec]
+    pack = [lat(*a) for a in spec]
+    for L in solo:
+        L.run_primal(200)
+        L.run_primal(61, accumulate=True)
+    g = H.Group()
+    g.set(pack, [H.GROUP_PRIMAL] * 2)
+    g.step(200)
+    g.set(pack, [H.GROUP_PRIMAL_WINDOW] * 2)
+    g.step(61)
+    g.synchronize()
+    for a, b in zip(solo, pack):
+        assert np.array_equal(a.populations(), b.populations())
+        assert a.window_objective() == b.window_objective()
+    for L in solo:
+        L.solve_adjoint(H.SOURCE_MEAN, tau_adj=0.6, max_iters=150)
+    for L in pack:
+        L.solve_adjoint(H.SOURCE_MEAN, tau_adj=0.6, max_iters=0)
+    g.set(pack, [H.GROUP_ADJOINT] * 2)
+    g.step(150)
+    g.synchronize()
+    for a, b in zip(solo, pack):
+        assert np.array_equal(a.adjoint(), b.adjoint())
+        assert np.array_equal(a.gradient(), b.gradient())
+
+
 def test_group_member_matches_oracle_fp64():
     from paper_2606_31707_amd import hlbm as H
     say("group vs oracle")
