@@ -389,7 +389,8 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
 // One lattice update of cell (x, y, z) (inside the lattice).
 // ACC: 0 no window; 1 window with the moment-form objective terms; 2 window
 // with J_MEA (its own terms; a separate instantiation keeps the register
-// budget of the common case).
+// budget of the common case); 3 window statistics only, the objective terms
+// of a small region being accumulated by k_window_region before the step.
 template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
                                             const typename Prec<S>::Dd* __restrict__ dpor,
@@ -451,7 +452,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
     if (acc.tau) acc.tau[cell] += (double)taue;
     int64_t r;
-    if (region_index<Q>(ob, x, y, z, r)) {
+    if (ACC != 3 && region_index<Q>(ob, x, y, z, r)) {
       double sd[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
@@ -712,6 +713,41 @@ __global__ __launch_bounds__(256) void k_tangent_objective(const Geo g, const Ob
     partials[linear_block()] = a;
     partials[nb + linear_block()] = b;
   }
+}
+
+// Objective terms of one window sample over the region only (grid over the
+// region box), from the canonical pre-collision state: the same values and
+// arithmetic as the fused window step, for regions much smaller than the
+// lattice (a drag plane, a surface box).  Launched before the step.
+template <int Q, typename S, bool MEA>
+__global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox ob, const S* __restrict__ A,
+                                                       const S* __restrict__ ghost, int parity,
+                                                       const typename Prec<S>::Dd* __restrict__ dpor,
+                                                       double* __restrict__ acc_obj) {
+  using T = typename Prec<S>::T;
+  const int x = ob.lo[0] + blockIdx.x * BX + threadIdx.x;
+  const int y = ob.lo[1] + blockIdx.y * BY + threadIdx.y;
+  const int z = ob.lo[2] + blockIdx.z;
+  int64_t r;
+  if (x >= g.nx || y >= g.ny || !region_index<Q>(ob, x, y, z, r)) return;
+  if (g.bcx == BC_INOUT && x == 0) return;  // the pinned inlet column is not sampled
+  const int64_t cell = cell_of(g, x, y, z);
+  T s[Q];
+  load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
+  double sd[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
+  double terms[Coef<Q>::N];
+  if constexpr (MEA) {
+    mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
+  } else {
+    double dr, ax, ay, az, P[6];
+    cell_moments<Q, double>(sd, dr, ax, ay, az);
+    neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
+    objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
+  }
+#pragma unroll
+  for (int m = 0; m < Coef<Q>::N; ++m) acc_obj[m * ob.rplane + r] += terms[m];
 }
 
 // Packed launch: one workgroup grid covering several lattices of one stencil

@@ -100,14 +100,35 @@ static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
     launch_k(k_primal<Q, S, true, ACC, HRR>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
 }
 
+// Window steps: the objective terms are fused into the sweep when the
+// region is a sizeable part of the lattice, and accumulated by a separate
+// region pass (before the step, from the same pre-collision state) when it is
+// small, so that the sweep keeps the register budget of a plain step.
 template <int Q, typename S, bool HRR>
 static void primal_mode(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
-  if (!accumulate)
+  if (!accumulate) {
     primal_variant<Q, S, 0, HRR>(L, e0, e1);
-  else if (L->obj_set && L->obj_kind == HLBM_OBJ_MEA)
+    return;
+  }
+  const bool mea = L->obj_set && L->obj_kind == HLBM_OBJ_MEA;
+  const int64_t rcells = (int64_t)L->rn[0] * L->rn[1] * L->rn[2];
+  if (L->obj_set && rcells * 8 <= L->n) {
+    using Dd = typename Prec<S>::Dd;
+    const dim3 rg((L->rn[0] + BX - 1) / BX, (L->rn[1] + BY - 1) / BY, L->rn[2]);
+    if (mea)
+      k_window_region<Q, S, true><<<rg, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+                                                                (const S*)L->ghost, L->parity,
+                                                                (const Dd*)L->dpor, L->acc_obj);
+    else
+      k_window_region<Q, S, false><<<rg, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+                                                                 (const S*)L->ghost, L->parity,
+                                                                 (const Dd*)L->dpor, L->acc_obj);
+    primal_variant<Q, S, 3, HRR>(L, e0, e1);
+  } else if (mea) {
     primal_variant<Q, S, 2, HRR>(L, e0, e1);
-  else
+  } else {
     primal_variant<Q, S, 1, HRR>(L, e0, e1);
+  }
 }
 
 template <int Q, typename S>
