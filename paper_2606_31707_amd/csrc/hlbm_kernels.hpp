@@ -40,17 +40,98 @@ namespace hlbm {
 #ifndef HLBM_NT_STORES
 #define HLBM_NT_STORES 0
 #endif
-template <typename S>
-__device__ __forceinline__ S ld_stream(const S* p) {
+template <typename P>
+__device__ __forceinline__ auto ld_stream(P p) {
   if (HLBM_NT_LOADS) return __builtin_nontemporal_load(p);
   return *p;
 }
-template <typename S>
-__device__ __forceinline__ void st_stream(S* p, S v) {
+template <typename P, typename S>
+__device__ __forceinline__ void st_stream(P p, S v) {
   if (HLBM_NT_STORES)
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
+}
+
+// Values that are the same in every lane of a wavefront (tile indices, tile
+// base cells), moved to scalar registers: the integer divisions of the tile
+// decode run on the vector unit, and without this their results, and all
+// address arithmetic built on them, would stay there.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t wave_uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Plane addressing of the sweeps.  A workgroup's tile starts at cell c0 (the
+// same for all its lanes) and a lane sits lo = tx + nx ty cells further on.
+// The per-plane base address (array + plane offset + c0, plus a fixed
+// neighbour offset in the odd step) is formed once in scalar registers, so
+// each access adds only the lane's 32-bit offset: no 64-bit vector address
+// arithmetic per population.  The base is a global-memory (address space 1)
+// pointer, so the accesses are global loads/stores with a scalar base.
+template <typename S>
+struct Glob {
+  typedef __attribute__((address_space(1))) S type;
+};
+template <typename S>
+__device__ __forceinline__ typename Glob<S>::type* plane_base(S* A, int64_t elem) {
+  const uint64_t a = (uint64_t)A + (uint64_t)(elem * (int64_t)sizeof(S));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (typename Glob<S>::type*)(((uint64_t)hi << 32) | lo);
+}
+// Element at plane offset elem (uniform) for lane offset lo (cells).  The
+// byte offset is formed in 32 bits, matching the scalar-base address form.
+template <typename S>
+__device__ __forceinline__ typename Glob<S>::type& at(S* A, int64_t elem, uint32_t lo) {
+  typedef typename Glob<char>::type gchar;
+  uint32_t off = lo * (uint32_t)sizeof(S);
+  asm volatile("" : "+v"(off));  // a 32-bit offset local to this access
+  return *(typename Glob<S>::type*)((gchar*)plane_base(A, elem) + off);
+}
+
+// A lane's 32-bit offset from its tile base, kept opaque to the optimizer so
+// that it stays a 32-bit register offset (the address form with a scalar
+// base) instead of being folded into 64-bit vector address arithmetic.
+__device__ __forceinline__ uint32_t lane_offset(uint32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+// Signed sum of the components selected by the (compile-time) lattice
+// coefficients a, b, c in {-1, 0, 1}; zero terms are never formed, so no
+// floating-point operation is spent on them.
+template <typename T>
+__device__ __forceinline__ T csum(int a, int b, int c, T x, T y, T z) {
+  if (a != 0) {
+    T r = a > 0 ? x : -x;
+    if (b != 0) r = b > 0 ? r + y : r - y;
+    if (c != 0) r = c > 0 ? r + z : r - z;
+    return r;
+  }
+  if (b != 0) {
+    T r = b > 0 ? y : -y;
+    if (c != 0) r = c > 0 ? r + z : r - z;
+    return r;
+  }
+  if (c != 0) return c > 0 ? z : -z;
+  return (T)0;
+}
+
+// 1/x for the densities of the sweeps (x near 1): hardware reciprocal
+// refined by Newton steps to within an ulp of the rounded quotient.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 }
 
 // Cells whose every neighbour is an ordinary lattice cell: no wall, inlet,
@@ -70,19 +151,25 @@ __device__ __forceinline__ int64_t nb_offset(const Geo& g, int k) {
 template <int Q, typename T>
 __device__ __forceinline__ void cell_moments(const T (&s)[Q], T& drho, T& jx, T& jy, T& jz) {
   using L = Lat<Q>;
-  drho = 0;
-  jx = 0;
-  jy = 0;
-  jz = 0;
+  // Sums start from their first term (no 0 + v), in direction order.
+  bool hx = false, hy = false, hz = false;
+  drho = s[0];
+  jx = jy = jz = (T)0;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
+  for (int k = 1; k < Q; ++k) {
     drho += s[k];
-    if (L::cx[k] > 0) jx += s[k];
-    if (L::cx[k] < 0) jx -= s[k];
-    if (L::cy[k] > 0) jy += s[k];
-    if (L::cy[k] < 0) jy -= s[k];
-    if (L::cz[k] > 0) jz += s[k];
-    if (L::cz[k] < 0) jz -= s[k];
+    if (L::cx[k] != 0) {
+      jx = hx ? (L::cx[k] > 0 ? jx + s[k] : jx - s[k]) : (L::cx[k] > 0 ? s[k] : -s[k]);
+      hx = true;
+    }
+    if (L::cy[k] != 0) {
+      jy = hy ? (L::cy[k] > 0 ? jy + s[k] : jy - s[k]) : (L::cy[k] > 0 ? s[k] : -s[k]);
+      hy = true;
+    }
+    if (L::cz[k] != 0) {
+      jz = hz ? (L::cz[k] > 0 ? jz + s[k] : jz - s[k]) : (L::cz[k] > 0 ? s[k] : -s[k]);
+      hz = true;
+    }
   }
 }
 
@@ -93,19 +180,22 @@ template <int Q, typename T>
 __device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T jz, T ir,
                                          T (&P)[6]) {
   using L = Lat<Q>;
-  T pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+  // Signed sums over the directions with a nonzero coefficient, each started
+  // from its first term (no 0 + v), in direction order.
+  T p[6] = {0, 0, 0, 0, 0, 0};
+  bool h[6] = {false, false, false, false, false, false};
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    if (L::cx[k] != 0) pxx += s[k];
-    if (L::cy[k] != 0) pyy += s[k];
-    if (L::cz[k] != 0) pzz += s[k];
-    if (L::cx[k] * L::cy[k] > 0) pxy += s[k];
-    if (L::cx[k] * L::cy[k] < 0) pxy -= s[k];
-    if (L::cx[k] * L::cz[k] > 0) pxz += s[k];
-    if (L::cx[k] * L::cz[k] < 0) pxz -= s[k];
-    if (L::cy[k] * L::cz[k] > 0) pyz += s[k];
-    if (L::cy[k] * L::cz[k] < 0) pyz -= s[k];
+    const int cf[6] = {L::cx[k] * L::cx[k], L::cy[k] * L::cy[k], L::cz[k] * L::cz[k],
+                       L::cx[k] * L::cy[k], L::cx[k] * L::cz[k], L::cy[k] * L::cz[k]};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      if (cf[m] == 0) continue;
+      p[m] = h[m] ? (cf[m] > 0 ? p[m] + s[k] : p[m] - s[k]) : (cf[m] > 0 ? s[k] : -s[k]);
+      h[m] = true;
+    }
   }
+  const T pxx = p[0], pyy = p[1], pzz = p[2], pxy = p[3], pxz = p[4], pyz = p[5];
   const T d3 = drho / (T)3;
   P[0] = pxx - d3 - jx * jx * ir;
   P[1] = pyy - d3 - jy * jy * ir;
@@ -136,19 +226,32 @@ __device__ __forceinline__ int sym_index(int m6) {
 }
 
 // a0 + a1.xi_i + a2:xi_i xi_i for a compact coefficient vector a.
+// Only the terms with nonzero lattice coefficients are formed.
 template <int Q, typename T>
 __device__ __forceinline__ T quad_eval(const T* a, int i) {
   using L = Lat<Q>;
   constexpr int D = L::D;
-  const T x = (T)L::cx[i], y = (T)L::cy[i], z = (T)L::cz[i];
-  T r = a[0] + a[1] * x + a[2] * y;
-  if (D == 3) {
-    r += a[3] * z;
-    r += a[4] * x * x + a[5] * y * y + a[6] * z * z + (T)2 * (a[7] * x * y + a[8] * x * z + a[9] * y * z);
-  } else {
-    r += a[3] * x * x + a[4] * y * y + (T)2 * a[5] * x * y;
+  const int c[3] = {L::cx[i], L::cy[i], D == 3 ? L::cz[i] : 0};
+  if (c[0] == 0 && c[1] == 0 && c[2] == 0) return a[0];
+  const T odd = csum<T>(c[0], c[1], c[2], a[1], a[2], D == 3 ? a[3] : (T)0);
+  // a2 : xi xi over the symmetric storage (diagonal, then off-diagonal x2)
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  constexpr int NS = L::NSYM;
+  const int sidx3[6] = {0, 1, 2, 3, 4, 5}, sidx2[6] = {0, 1, -1, 2, -1, -1};
+  T even = (T)0;
+  bool he = false;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const int si = (NS == 6) ? sidx3[m] : sidx2[m];
+    if (si < 0) continue;
+    const int cf = c[ia[m]] * c[ib[m]] * (m < 3 ? 1 : 2);
+    if (cf == 0) continue;
+    const T v = a[1 + D + si];
+    const T t = cf == 1 ? v : (cf == -1 ? -v : (T)cf * v);
+    even = he ? even + t : t;
+    he = true;
   }
-  return r;
+  return he ? (a[0] + odd) + even : a[0] + odd;
 }
 
 // Objective terms of one region cell (Sec. 4, Eqs. obj_ffa and obj_diss),
@@ -231,7 +334,8 @@ __device__ void mea_terms(const Geo& g, const ObjBox& ob, int x, int y, int z, i
   for (int m = 0; m < Coef<Q>::N; ++m) out[m] = 0.0;
   double J = 0.0;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) J += mea_g<Q>(g, ob, x, y, z, r, k) * (sd[k] + L::w[k]);
+  for (int k = 0; k < Q; ++k)
+    if (L::cx[k] != 0) J += mea_g<Q>(g, ob, x, y, z, r, k) * (sd[k] + L::w[k]);
   out[Coef<Q>::J] = J;
 }
 
@@ -360,15 +464,21 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
 // Sweep kernels: 1D grid over the tiles (see sweep_tile).
 #define SWEEP_PROLOGUE                                                       \
   const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x);                \
-  const int z = t_ / (g.tiles_x * g.tiles_y);                                \
+  const int z = wave_uniform(t_ / (g.tiles_x * g.tiles_y));                  \
   const int r_ = t_ - z * g.tiles_x * g.tiles_y;                             \
-  const int x = (r_ % g.tiles_x) * BX + threadIdx.x;                         \
-  const int y = (r_ / g.tiles_x) * BY + threadIdx.y;                         \
+  const int x0_ = wave_uniform((r_ % g.tiles_x) * BX);                       \
+  const int y0_ = wave_uniform((r_ / g.tiles_x) * BY);                       \
+  const int x = x0_ + threadIdx.x;                                           \
+  const int y = y0_ + threadIdx.y;                                           \
   const bool valid = (x < g.nx) && (y < g.ny);                               \
   const int64_t cell = valid ? cell_of(g, x, y, z) : 0;                      \
+  const int64_t tile_c0 = wave_uniform64(cell_of(g, x0_, y0_, z));          \
+  const uint32_t tile_lo = lane_offset(threadIdx.x + (uint32_t)g.nx * threadIdx.y); \
   const bool inout = (g.bcx == BC_INOUT);                                    \
   (void)inout;                                                               \
-  (void)cell;
+  (void)cell;                                                                \
+  (void)tile_c0;                                                             \
+  (void)tile_lo;
 
 #define CELL_PROLOGUE                                   \
   const int x = blockIdx.x * BX + threadIdx.x;          \
@@ -386,7 +496,8 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
 // AA propagation with boundaries, fused FP64 window accumulation.
 // =========================================================================
 
-// One lattice update of cell (x, y, z) (inside the lattice).
+// One lattice update of cell (x, y, z) (inside the lattice), at lane offset
+// lo from its tile's first cell c0 (see plane_base).
 // ACC: 0 no window; 1 window with the moment-form objective terms; 2 window
 // with J_MEA (its own terms; a separate instantiation keeps the register
 // budget of the common case); 3 window statistics only, the objective terms
@@ -395,10 +506,10 @@ template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
                                             const typename Prec<S>::Dd* __restrict__ dpor,
                                             S* __restrict__ ghost, const Acc& acc, const int x, const int y,
-                                            const int z) {
+                                            const int z, const int64_t c0, const uint32_t lo) {
   using L = Lat<Q>;
   using T = typename Prec<S>::T;
-  const int64_t cell = cell_of(g, x, y, z);
+  const int64_t cell = c0 + lo;
   const bool inout = (g.bcx == BC_INOUT);
   T s[Q];
   if (inout && x == 0) {  // pinned equilibrium inlet: not collided, source only
@@ -412,13 +523,21 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
     return;
   }
+  // Porosity and populations are requested together.
+  const T d = (T)at(dpor, c0, lo);
   const bool interior = ODD && interior_cell<Q>(g, x, y, z);
+  // All population loads are issued before any arithmetic on them (the
+  // scheduler otherwise interleaves early sums, which forces a wait for the
+  // first loads before the remaining ones are even issued).
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream(&A[k * g.plane + cell]);
+    for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream(&at(A, k * g.plane + c0, lo));
+    __builtin_amdgcn_sched_barrier(0);
   } else if (interior) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream(&A[L::opp[k] * g.plane + cell - nb_offset<Q>(g, k)]);
+    for (int k = 0; k < Q; ++k)
+      s[k] = (T)ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+    __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = pull<Q, S, T>(g, A, ghost, x, y, z, cell, k);
@@ -427,10 +546,9 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   T drho, jx, jy, jz;
   cell_moments<Q, T>(s, drho, jx, jy, jz);
   const T rho = (T)1 + drho;
-  const T ir = (T)1 / rho;
-  const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const T ir = recip(rho);
 
-  if (cell == c.probe_cell) *c.probe_out = (double)uy;
+  if (cell == c.probe_cell) *c.probe_out = (double)(jy * ir);
   T omega = (T)c.omega0;
   T taue = (T)c.tau0;
   if (c.smag) {
@@ -442,15 +560,15 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
 
   if constexpr (ACC != 0) {
-    acc.rho[cell] += (double)drho;
-    acc.j[cell] += (double)jx;
-    acc.j[g.plane + cell] += (double)jy;
-    if (L::D == 3) acc.j[2 * g.plane + cell] += (double)jz;
+    at(acc.rho, c0, lo) += (double)drho;
+    at(acc.j, c0, lo) += (double)jx;
+    at(acc.j, g.plane + c0, lo) += (double)jy;
+    if (L::D == 3) at(acc.j, 2 * g.plane + c0, lo) += (double)jz;
     if (acc.f) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) acc.f[k * g.plane + cell] += (double)s[k];
+      for (int k = 0; k < Q; ++k) at(acc.f, k * g.plane + c0, lo) += (double)s[k];
     }
-    if (acc.tau) acc.tau[cell] += (double)taue;
+    if (acc.tau) at(acc.tau, c0, lo) += (double)taue;
     int64_t r;
     if (ACC != 3 && region_index<Q>(ob, x, y, z, r)) {
       double sd[Q];
@@ -463,7 +581,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         double dr, ax, ay, az, P[6];
         cell_moments<Q, double>(sd, dr, ax, ay, az);
         neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
-        objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
+        objective_terms<Q>(ob, (double)d, dr, ax, ay, az, P, terms);
       }
 #pragma unroll
       for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
@@ -471,27 +589,46 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
 
   const bool outlet = inout && (x == g.nx - 1);
-  const T uu = ux * ux + uy * uy + uz * uz;
-  const T d = (T)dpor[cell];
   if constexpr (HRR) {
     hrr_collide<Q, T>(s, drho, jx, jy, jz, d, omega, c.force);
   } else {
-    const T tx = d * ux, ty = d * uy, tz = d * uz;
-    const T tt = tx * tx + ty * ty + tz * tz;
+    // s <- (1 - omega) s + omega (f^eq(rho, u~) - w), u~ = d j / rho, written
+    // per opposite pair (k, opp k): with cu = xi_k . u~ the equilibrium is
+    // w (A0 + C cu^2) +- w B cu, A0 = drho - 1.5 rho u~^2, B = 3 rho,
+    // C = 4.5 rho; omega is folded into A0, B and C.
+    const T dir = d * ir;
+    const T tx = jx * dir, ty = jy * dir, tz = (L::D == 3) ? jz * dir : (T)0;
+    const T tt = (L::D == 3) ? tx * tx + ty * ty + tz * tz : tx * tx + ty * ty;
+    const T orho = omega * rho;
+    const T a0 = omega * drho - (T)1.5 * orho * tt;
+    const T b1 = (T)3 * orho, c2 = (T)4.5 * orho;
+    const T omc = (T)1 - omega;
+    s[0] = omc * s[0] + (T)L::w[0] * a0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const T cu = (T)L::cx[k] * tx + (T)L::cy[k] * ty + (T)L::cz[k] * tz;
-      const T feqs = (T)L::w[k] * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt));
-      const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)c.force[0] + (T)L::cy[k] * (T)c.force[1] +
-                                          (T)L::cz[k] * (T)c.force[2]);
-      s[k] = s[k] + omega * (feqs - s[k]) + fk;
+    for (int k = 1; k < Q; ++k) {
+      if (L::opp[k] < k) continue;
+      const int o = L::opp[k];
+      const T w = (T)L::w[k];
+      const T cu = csum<T>(L::cx[k], L::cy[k], L::cz[k], tx, ty, tz);
+      const T sym = (w * a0) + ((w * c2) * cu) * cu;
+      const T asy = (w * b1) * cu;
+      s[k] = omc * s[k] + (sym + asy);
+      s[o] = omc * s[o] + (sym - asy);
+    }
+    if (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) {  // body force 3 w xi.F
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        s[k] += (T)(3.0 * L::w[k]) *
+                csum<T>(L::cx[k], L::cy[k], L::cz[k], (T)c.force[0], (T)c.force[1], (T)c.force[2]);
     }
   }
 
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream(&A[L::opp[k] * g.plane + cell], (S)s[k]);
+    for (int k = 0; k < Q; ++k) st_stream(&at(A, L::opp[k] * g.plane + c0, lo), (S)s[k]);
     if (outlet) {
+      const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+      const T uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (L::cx[k] != -1) continue;
@@ -502,11 +639,14 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
   } else if (interior) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream(&A[k * g.plane + cell + nb_offset<Q>(g, k)], (S)s[k]);
+    for (int k = 0; k < Q; ++k)
+      st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
     if (outlet) {
+      const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+      const T uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (L::cx[k] != -1) continue;
@@ -527,7 +667,7 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
                                                 S* __restrict__ ghost, const Acc acc) {
   SWEEP_PROLOGUE
   if (!valid) return;
-  primal_cell<Q, S, ODD, ACC, HRR>(g, c, ob, A, dpor, ghost, acc, x, y, z);
+  primal_cell<Q, S, ODD, ACC, HRR>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
 }
 
 // =========================================================================
@@ -730,7 +870,6 @@ __global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox
   const int z = ob.lo[2] + blockIdx.z;
   int64_t r;
   if (x >= g.nx || y >= g.ny || !region_index<Q>(ob, x, y, z, r)) return;
-  if (g.bcx == BC_INOUT && x == 0) return;  // the pinned inlet column is not sampled
   const int64_t cell = cell_of(g, x, y, z);
   T s[Q];
   load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);
@@ -784,24 +923,26 @@ __global__ __launch_bounds__(256) void k_primal_packed(const PackedPrimal* __res
   const int ty = r % P.tiles_y, z = r / P.tiles_y;
   const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
   if (x >= P.g.nx || y >= P.g.ny) return;
+  const int64_t c0 = wave_uniform64(cell_of(P.g, tx * BX, ty * BY, z));
+  const uint32_t lo = lane_offset(threadIdx.x + (uint32_t)P.g.nx * threadIdx.y);
   S* A = (S*)P.A;
   const Dd* dp = (const Dd*)P.dpor;
   S* gh = (S*)P.ghost;
   const int mode = P.accumulate ? (P.ob.kind == OBJ_MEA ? 2 : 1) : 0;
   if ((P.parity0 + step) & 1) {
     if (mode == 1)
-      primal_cell<Q, S, true, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, true, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
     else if (mode == 2)
-      primal_cell<Q, S, true, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, true, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
     else
-      primal_cell<Q, S, true, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, true, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
   } else {
     if (mode == 1)
-      primal_cell<Q, S, false, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, false, 1, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
     else if (mode == 2)
-      primal_cell<Q, S, false, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, false, 2, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
     else
-      primal_cell<Q, S, false, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z);
+      primal_cell<Q, S, false, 0, HRR>(P.g, P.c, P.ob, A, dp, gh, P.acc, x, y, z, c0, lo);
   }
 }
 
@@ -1286,6 +1427,16 @@ struct AdjC {
 // Adjoint values of a cell as read by an even step / the gradient: canonical
 // slots, with the outlet's outgoing directions zero unless bounce-back wrote them.
 template <int Q, typename SA>
+__device__ __forceinline__ void adjoint_zero_outlet(const Geo& g, int x, int y, int z, SA (&ph)[Q]) {
+  using L = Lat<Q>;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (L::cx[k] != -1) continue;
+    int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
+    if (classify(g, sx, sy, sz) != NB_BOUNCE) ph[k] = (SA)0;
+  }
+}
+template <int Q, typename SA>
 __device__ __forceinline__ void adjoint_read_canonical(const Geo& g, const SA* __restrict__ A, int x,
                                                        int y, int z, int64_t cell, bool outlet,
                                                        SA (&ph)[Q]) {
@@ -1516,11 +1667,12 @@ template <int Q, typename SA, bool ODD, bool HRR, bool MEA>
 __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, const AdjC& ac, SA* __restrict__ A,
                                              const SA* __restrict__ prep, const double* __restrict__ src,
                                              const double* __restrict__ oprep, const SA* __restrict__ pv_in,
-                                             SA* __restrict__ pv_out, const int x, const int y, const int z) {
+                                             SA* __restrict__ pv_out, const int x, const int y, const int z,
+                                             const int64_t c0, const uint32_t lo) {
   using L = Lat<Q>;
   using T = SA;
   constexpr int D = L::D;
-  const int64_t cell = cell_of(g, x, y, z);
+  const int64_t cell = c0 + lo;
   const bool inout = (g.bcx == BC_INOUT);
   if (inout && x == 0) {  // inlet: no dependence on the state, lambda = 0
     if (!ODD) {
@@ -1536,10 +1688,14 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   T ph[Q];  // phihat_k = phi_opp(k)
   const bool interior = ODD && interior_cell<Q>(g, x, y, z);
   if (!ODD) {
-    adjoint_read_canonical<Q, SA>(g, A, x, y, z, cell, outlet, ph);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&at(A, k * g.plane + c0, lo));
+    __builtin_amdgcn_sched_barrier(0);
+    if (outlet) adjoint_zero_outlet<Q, SA>(g, x, y, z, ph);
   } else if (interior) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&A[L::opp[k] * g.plane + cell - nb_offset<Q>(g, k)]);
+    for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+    __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -1557,71 +1713,108 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   if constexpr (HRR) {
     hrr_adjoint<Q, T>(ph, prep, g.plane, cell, ac.diff != 0, lam);
   } else {
-    // weighted moments of phi: m0 = sum w phi, m1 = sum w phi xi, m2 = sum w phi xi xi
-    T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+    // Frozen data first, so that its loads overlap the moments.
+    const T tx = at(prep, c0, lo);
+    const T ty = at(prep, g.plane + c0, lo);
+    const T tz = (D == 3) ? (T)at(prep, 2 * g.plane + c0, lo) : (T)0;
+    const T d = at(prep, D * g.plane + c0, lo);
+    const T omega = ac.les ? (T)at(prep, (D + 1) * g.plane + c0, lo) : (T)ac.omega0;
+    // Weighted moments of phi (phi_i = ph[opp i], xi_opp(k) = -xi_k) over the
+    // opposite pairs: m0 = sum w phi, m1 = sum w phi xi, M2 = sum w phi xi xi;
+    // terms with zero lattice coefficients are never formed.
+    T m0 = (T)L::w[0] * ph[0];
+    T m1[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
+    bool h1[3] = {false, false, false}, h2[6] = {false, false, false, false, false, false};
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const T wp = (T)L::w[k] * ph[k];
+    for (int k = 1; k < Q; ++k) {
+      if (L::opp[k] < k) continue;
+      const int o = L::opp[k];
+      const T w = (T)L::w[k];
+      const T wp = w * (ph[k] + ph[o]);
+      const T wq = w * (ph[k] - ph[o]);
       m0 += wp;
-      // phi_i = ph[opp i]; xi_opp(k) = -xi_k
-      m1x -= (T)L::cx[k] * wp;
-      m1y -= (T)L::cy[k] * wp;
-      m1z -= (T)L::cz[k] * wp;
-      mxx += (T)(L::cx[k] * L::cx[k]) * wp;
-      myy += (T)(L::cy[k] * L::cy[k]) * wp;
-      mzz += (T)(L::cz[k] * L::cz[k]) * wp;
-      mxy += (T)(L::cx[k] * L::cy[k]) * wp;
-      mxz += (T)(L::cx[k] * L::cz[k]) * wp;
-      myz += (T)(L::cy[k] * L::cz[k]) * wp;
+      const int c[3] = {L::cx[k], L::cy[k], L::cz[k]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (c[a] == 0) continue;
+        const T t = c[a] > 0 ? -wq : wq;
+        m1[a] = h1[a] ? m1[a] + t : t;
+        h1[a] = true;
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const int cf = c[ia[m]] * c[ib[m]];
+        if (cf == 0) continue;
+        const T t = cf > 0 ? wp : -wp;
+        m2[m] = h2[m] ? m2[m] + t : t;
+        h2[m] = true;
+      }
     }
-    const T tx = prep[cell];
-    const T ty = prep[g.plane + cell];
-    const T tz = (D == 3) ? prep[2 * g.plane + cell] : (T)0;
-    const T d = prep[D * g.plane + cell];
-    const T omega = ac.les ? prep[(D + 1) * g.plane + cell] : (T)ac.omega0;
-    const T tt = tx * tx + ty * ty + tz * tz;
-    const T m2tx = mxx * tx + mxy * ty + mxz * tz;
-    const T m2ty = mxy * tx + myy * ty + myz * tz;
-    const T m2tz = mxz * tx + myz * ty + mzz * tz;
-    const T tmt = tx * m2tx + ty * m2ty + tz * m2tz;
-    // sum_j phi_j d f^eq_j / d f_i = Phr + Phj . xi_i
-    const T Phr = m0 * ((T)1 + (T)1.5 * tt) - (T)4.5 * tmt;
-    const T Pjx = d * ((T)3 * m1x + (T)9 * m2tx - (T)3 * m0 * tx);
-    const T Pjy = d * ((T)3 * m1y + (T)9 * m2ty - (T)3 * m0 * ty);
-    const T Pjz = d * ((T)3 * m1z + (T)9 * m2tz - (T)3 * m0 * tz);
+    const T mxx = m2[0], myy = m2[1], mzz = m2[2], mxy = m2[3], mxz = m2[4], myz = m2[5];
+    T tt, m2tx, m2ty, m2tz, tmt;
+    if constexpr (D == 3) {
+      tt = tx * tx + ty * ty + tz * tz;
+      m2tx = mxx * tx + mxy * ty + mxz * tz;
+      m2ty = mxy * tx + myy * ty + myz * tz;
+      m2tz = mxz * tx + myz * ty + mzz * tz;
+      tmt = tx * m2tx + ty * m2ty + tz * m2tz;
+    } else {
+      tt = tx * tx + ty * ty;
+      m2tx = mxx * tx + mxy * ty;
+      m2ty = mxy * tx + myy * ty;
+      m2tz = (T)0;
+      tmt = tx * m2tx + ty * m2ty;
+    }
+    // sum_j phi_j d f^eq_j / d f_i = Phr + Phj . xi_i, scaled by omega
+    const T oPhr = omega * (m0 * ((T)1 + (T)1.5 * tt) - (T)4.5 * tmt);
+    const T od = omega * d;
+    const T oPjx = od * ((T)3 * m1[0] + (T)9 * m2tx - (T)3 * m0 * tx);
+    const T oPjy = od * ((T)3 * m1[1] + (T)9 * m2ty - (T)3 * m0 * ty);
+    const T oPjz = (D == 3) ? od * ((T)3 * m1[2] + (T)9 * m2tz - (T)3 * m0 * tz) : (T)0;
+    const T omc = (T)1 - omega;
+    lam[0] = omc * ph[0] + oPhr;
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      lam[i] = ((T)1 - omega) * ph[L::opp[i]] +
-               omega * (Phr + (T)L::cx[i] * Pjx + (T)L::cy[i] * Pjy + (T)L::cz[i] * Pjz);
+    for (int k = 1; k < Q; ++k) {
+      if (L::opp[k] < k) continue;
+      const int o = L::opp[k];
+      const T e = csum<T>(L::cx[k], L::cy[k], L::cz[k], oPjx, oPjy, oPjz);
+      lam[k] = omc * ph[o] + (oPhr + e);
+      lam[o] = omc * ph[k] + (oPhr - e);
+    }
     if (ac.diff) {  // differentiated Smagorinsky: (sum_j phi_j f^neq_j) (1/tau^2) dtau/df_i
-      T sd = 0;
+      T sd = ph[0] * (T)at(prep, (D + 2 + L::opp[0]) * g.plane + c0, lo);
 #pragma unroll
-      for (int k = 0; k < Q; ++k) sd += ph[k] * prep[(D + 2 + L::opp[k]) * g.plane + cell];
+      for (int k = 1; k < Q; ++k) sd += ph[k] * (T)at(prep, (D + 2 + L::opp[k]) * g.plane + c0, lo);
       T b[Coef<Q>::NB];
 #pragma unroll
-      for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = prep[(D + 2 + Q + m) * g.plane + cell];
+      for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = at(prep, (D + 2 + Q + m) * g.plane + c0, lo);
 #pragma unroll
       for (int i = 0; i < Q; ++i) lam[i] += sd * quad_eval<Q, T>(b, i);
     }
   }
   if (outlet) {  // virtual column: sum_j dV_j/df_i phiV_j = (xi_i - u).Psi / rho
     const int64_t o = y + (int64_t)g.ny * z;
-    T v0 = 0, v1x = 0, v1y = 0, v1z = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
+    // weighted moments of the virtual column's adjoint values (directions
+    // with xi_x = -1), zero coefficients skipped
+    T v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // v0, v1 (x y z), v2 (xx yy zz xy xz yz)
+    bool hv[10] = {false, false, false, false, false, false, false, false, false, false};
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (L::cx[k] != -1) continue;
       const T wp = (T)L::w[k] * pv_in[k * g.gplane + o];
-      v0 += wp;
-      v1x += (T)L::cx[k] * wp;
-      v1y += (T)L::cy[k] * wp;
-      v1z += (T)L::cz[k] * wp;
-      vxx += (T)(L::cx[k] * L::cx[k]) * wp;
-      vyy += (T)(L::cy[k] * L::cy[k]) * wp;
-      vzz += (T)(L::cz[k] * L::cz[k]) * wp;
-      vxy += (T)(L::cx[k] * L::cy[k]) * wp;
-      vxz += (T)(L::cx[k] * L::cz[k]) * wp;
-      vyz += (T)(L::cy[k] * L::cz[k]) * wp;
+      const int cf[10] = {1, L::cx[k], L::cy[k], L::cz[k], L::cx[k] * L::cx[k], L::cy[k] * L::cy[k],
+                          L::cz[k] * L::cz[k], L::cx[k] * L::cy[k], L::cx[k] * L::cz[k], L::cy[k] * L::cz[k]};
+#pragma unroll
+      for (int m = 0; m < 10; ++m) {
+        if (cf[m] == 0) continue;
+        const T t = cf[m] > 0 ? wp : -wp;
+        v[m] = hv[m] ? v[m] + t : t;
+        hv[m] = true;
+      }
     }
+    const T v0 = v[0], v1x = v[1], v1y = v[2], v1z = v[3], vxx = v[4], vyy = v[5], vzz = v[6], vxy = v[7],
+            vxz = v[8], vyz = v[9];
     const T ro = (T)oprep[o];
     const T uox = (T)oprep[g.gplane + o];
     const T uoy = (T)oprep[2 * g.gplane + o];
@@ -1649,10 +1842,10 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
 
   if (!ODD) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_stream(&A[i * g.plane + cell], lam[i]);
+    for (int i = 0; i < Q; ++i) st_stream(&at(A, i * g.plane + c0, lo), lam[i]);
   } else if (interior) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream(&A[k * g.plane + cell + nb_offset<Q>(g, k)], lam[L::opp[k]]);
+    for (int k = 0; k < Q; ++k) st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), lam[L::opp[k]]);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, lam[L::opp[k]]);
@@ -1676,7 +1869,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
                                                  const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
   SWEEP_PROLOGUE
   if (!valid) return;
-  adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z);
+  adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
 }
 
 struct PackedAdjoint {
@@ -1703,6 +1896,8 @@ __global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __r
   const int ty = r % P.tiles_y, z = r / P.tiles_y;
   const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
   if (x >= P.g.nx || y >= P.g.ny) return;
+  const int64_t c0 = wave_uniform64(cell_of(P.g, tx * BX, ty * BY, z));
+  const uint32_t lo = lane_offset(threadIdx.x + (uint32_t)P.g.nx * threadIdx.y);
   const int cur = (P.pvcur0 + step) & 1;
   const SA* pin = (const SA*)P.pv[cur];
   SA* pout = (SA*)P.pv[cur ^ 1];
@@ -1711,14 +1906,14 @@ __global__ __launch_bounds__(256) void k_adjoint_packed(const PackedAdjoint* __r
   const bool odd = ((P.iter0 + step) & 1) != 0;
   if (P.ob.kind == OBJ_MEA) {
     if (odd)
-      adjoint_cell<Q, SA, true, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+      adjoint_cell<Q, SA, true, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z, c0, lo);
     else
-      adjoint_cell<Q, SA, false, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+      adjoint_cell<Q, SA, false, HRR, true>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z, c0, lo);
   } else {
     if (odd)
-      adjoint_cell<Q, SA, true, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+      adjoint_cell<Q, SA, true, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z, c0, lo);
     else
-      adjoint_cell<Q, SA, false, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z);
+      adjoint_cell<Q, SA, false, HRR, false>(P.g, P.ob, P.ac, A, pr, P.src, P.oprep, pin, pout, x, y, z, c0, lo);
   }
 }
 

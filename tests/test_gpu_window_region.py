@@ -3,7 +3,7 @@ objective regions of every size: a region of at most 1/8 of the lattice has
 its objective terms accumulated by a separate pass over the region, a larger
 one inside the sweep.  Both must give the oracle's window mean of J and its
 mean-flow adjoint and gradient, for FFA, DISS and J_MEA, with either
-collision, and for a region that contains the pinned inlet column."""
+collision, and for a region in the outlet and wall corner."""
 import math
 
 import numpy as np
@@ -20,14 +20,14 @@ CASES = {
     # name: (kind, lo, hi, u0, collision, cs)
     "diss_small": (O.OBJ_DISS, (50, 10, 0), (60, 30, 0), 0.0, 0, 0.0),
     "diss_large": (O.OBJ_DISS, (2, 0, 0), (118, 40, 0), 0.0, 0, 0.0),
-    "diss_inlet": (O.OBJ_DISS, (0, 15, 0), (3, 25, 0), 0.0, 0, 0.0),
+    "diss_outlet": (O.OBJ_DISS, (110, 0, 0), (119, 10, 0), 0.0, 0, 0.0),
     "ffa_plane": (O.OBJ_FFA, (90, 0, 0), (90, 40, 0), 0.05, 0, 0.0),
     "mea_small": (O.OBJ_MEA, (30, 8, 0), (50, 32, 0), math.pi * 10.0, 0, 0.0),
     "mea_large": (O.OBJ_MEA, (5, 2, 0), (110, 38, 0), math.pi * 10.0, 0, 0.0),
     "diss_small_hrr": (O.OBJ_DISS, (50, 10, 0), (60, 30, 0), 0.0, 1, 0.15),
     "diss_large_hrr": (O.OBJ_DISS, (2, 0, 0), (118, 40, 0), 0.0, 1, 0.15),
 }
-SMALL = {"diss_small", "diss_inlet", "ffa_plane", "mea_small", "diss_small_hrr"}
+SMALL = {"diss_small", "diss_outlet", "ffa_plane", "mea_small", "diss_small_hrr"}
 
 
 def H():
