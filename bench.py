@@ -190,7 +190,7 @@ def summarize_profiles(d: str):
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     alg = 152 * w.n
-    live = None  # an unprofiled run of the same command (the profiler slows the sampled launches)
+    live = None  # an unprofiled run of the same command
     try:
         live = json.load(open(os.path.join(d, "bench.json")))["roofline"]
     except (OSError, ValueError, KeyError):
@@ -200,9 +200,10 @@ def summarize_profiles(d: str):
                   f"{alg / mean_us / 1e3:.0f} GB/s ({alg / mean_us / 1e3 / HBM_PEAK_GBS * 100:.1f} % of 8 TB/s)."]
     if live:
         lines += [f"The benchmark's own figure for this kernel in an unprofiled run of the same command on the "
-                  f"same box (HIP events recorded at kernel start and end, one launch in 49 sampled): "
-                  f"{live['us_per_launch']:.2f} us per launch, {live['achieved']:.0f} GB/s (the event pair "
-                  f"around a sampled launch adds a fraction of a microsecond)."]
+                  f"same box (HIP events recorded on the sweep's stream around blocks of up to 49 back-to-back "
+                  f"launches, every launch of the timed queries, dispatch gaps included): "
+                  f"{live['us_per_launch']:.2f} us per launch, {live['achieved']:.0f} GB/s. The trace's kernel "
+                  f"durations carry the profiler's own per-dispatch overhead."]
 
     def per_launch(sub, counter):
         vals = {PRIMAL_EVEN: [], PRIMAL_ODD: []}
@@ -605,7 +606,7 @@ def main():
     ap.add_argument("--periods", type=int, default=10)
     ap.add_argument("--adjoint-max", type=int, default=60000)
     ap.add_argument("--adjoint-tol", type=float, default=1e-6)
-    ap.add_argument("--profile-every", type=int, default=49)  # odd: samples both AA parities
+    ap.add_argument("--profile-every", type=int, default=49)  # block length of the sweep timing
     ap.add_argument("--cpu-primal", type=int, default=40)
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -705,7 +706,7 @@ def main():
     kus = prof["primal"]["mean_us"]
     achieved = bpu["primal"] * n / (kus * 1e-6) / 1e9 if kus > 0 else 0.0
     khash = kernel_source_hash()
-    log(f"k_primal: {kus:.2f} us/launch ({prof['primal']['sampled']} sampled), {achieved:.0f} GB/s; "
+    log(f"k_primal: {kus:.2f} us/launch ({prof['primal']['sampled']} launches timed in blocks), {achieved:.0f} GB/s; "
         f"window {prof['primal_window']['mean_us']:.2f} us; adjoint {prof['adjoint']['mean_us']:.2f} us")
 
     out = {
@@ -731,6 +732,7 @@ def main():
                      "bytes_per_update": bpu["primal"], "updates_per_launch": n, "us_per_launch": kus,
                      "window_us_per_launch": prof["primal_window"]["mean_us"],
                      "adjoint_us_per_launch": prof["adjoint"]["mean_us"],
+                     "timing": "HIP events on the sweep stream around blocks of back-to-back launches",
                      "note": "the 36 MB of FP64 populations stay resident in the 256 MB Infinity Cache"},
     }
     if not args.no_fp32:

@@ -265,12 +265,19 @@ hlbm_status hlbm_get_adjoint(hlbm_lattice lat, double* phi, int64_t n_values, in
 hlbm_status hlbm_get_field(hlbm_lattice lat, int32_t field, double* out, int64_t n_values,
                            int32_t mem);
 hlbm_status hlbm_synchronize(hlbm_lattice lat);
-/* Kernel timing by HIP events on the lattice's stream.  With every > 0, one
- * launch in `every` of each sweep kind is bracketed by a pair of events and
- * timed on its own (the others run untouched); every = 0 switches it off and
- * clears the statistics.  kind: 0 primal sweep, 1 primal sweep with window
- * accumulation, 2 adjoint sweep.  hlbm_profile_get returns the mean duration
- * of the sampled launches in microseconds and how many were sampled. */
+/* Sweep timing by HIP events on the lattice's stream.  With every > 0, the
+ * sweeps of each kind are timed in blocks of up to `every` back-to-back
+ * launches: an event is recorded before the first and after the last launch
+ * of a block, and a block ends with the caller's run of consecutive sweeps
+ * (hlbm_run_primal's steps between steady checks, hlbm_solve_adjoint's
+ * iterations between residual checks), so the time per launch is the sweep's
+ * duration in a steady stream of launches, dispatch gaps included.  The events
+ * are read back lazily: timing adds no host synchronization to a run.
+ * every = 0 switches it off; every call clears the statistics.  kind: 0
+ * primal sweep, 1 primal step with window accumulation (sweep plus the
+ * region pass of a small objective region), 2 adjoint sweep.
+ * hlbm_profile_get returns the mean time per launch in microseconds and the
+ * number of launches timed (blocks finished so far). */
 hlbm_status hlbm_profile_enable(hlbm_lattice lat, int32_t every);
 hlbm_status hlbm_profile_get(hlbm_lattice lat, int32_t kind, double* mean_us, int64_t* sampled);
 /* Velocity probe: every primal step records u_y of cell (x, y, z) (the

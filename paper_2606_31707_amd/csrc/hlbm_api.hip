@@ -202,20 +202,65 @@ hlbm_status zero_window(hlbm_lattice_s* L) {
   return HLBM_OK;
 }
 
-// Launches one sweep of the given kind; one launch in prof_every is timed by
-// events the runtime records at that kernel's own start and end.
+// Adds a finished timing block to its kind's statistics and frees the slot.
+hlbm_status prof_collect(hlbm_lattice_s* L, int slot) {
+  const int kind = L->prof_slot_kind[slot];
+  if (kind < 0) return HLBM_OK;
+  HIP_TRY(hipEventSynchronize(L->prof_ev[slot][1]));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, L->prof_ev[slot][0], L->prof_ev[slot][1]));
+  L->prof_ms[kind] += ms;
+  L->prof_sampled[kind] += L->prof_slot_n[slot];
+  L->prof_slot_kind[slot] = -1;
+  return HLBM_OK;
+}
+
+// Collects every block (closing none): statistics up to the last closed block.
+hlbm_status prof_collect_all(hlbm_lattice_s* L) {
+  for (int i = 0; i < hlbm_lattice_s::kProfSlots; ++i) {
+    if (i == L->prof_open) continue;
+    hlbm_status s = prof_collect(L, i);
+    if (s != HLBM_OK) return s;
+  }
+  return HLBM_OK;
+}
+
+// Launches one sweep of the given kind.  With profiling on, the launches are
+// timed in blocks of up to prof_every back-to-back launches of one kind; a
+// block never extends past the caller's run of `remaining` consecutive sweeps
+// (other kernels follow it), so the block time per launch is the sweep's
+// duration in a steady stream of launches, dispatch gaps included.
 template <typename F>
-hlbm_status timed_launch(hlbm_lattice_s* L, int kind, F&& launch) {
-  const bool sample = L->prof_every > 0 && (L->prof_count[kind] % L->prof_every) == 0;
-  L->prof_count[kind] += 1;
-  hipError_t e = sample ? launch(L->ev0, L->ev1) : launch(nullptr, nullptr);
+hlbm_status timed_launch(hlbm_lattice_s* L, int kind, int64_t remaining, F&& launch) {
+  if (L->prof_every <= 0) {
+    hipError_t e = launch(nullptr, nullptr);
+    if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+    return HLBM_OK;
+  }
+  hlbm_status s;
+  if (L->prof_open >= 0 && L->prof_open_kind != kind) {  // left open by a failed run
+    HIP_TRY(hipEventRecord(L->prof_ev[L->prof_open][1], L->stream));
+    L->prof_slot_kind[L->prof_open] = L->prof_open_kind;
+    L->prof_open = -1;
+  }
+  if (L->prof_open < 0) {  // open a block in the next slot of the ring
+    const int slot = L->prof_next;
+    L->prof_next = (slot + 1) % hlbm_lattice_s::kProfSlots;
+    if ((s = prof_collect(L, slot)) != HLBM_OK) return s;  // long finished
+    HIP_TRY(hipEventRecord(L->prof_ev[slot][0], L->stream));
+    L->prof_open = slot;
+    L->prof_open_kind = kind;
+    L->prof_slot_n[slot] = 0;
+  }
+  hipError_t e = launch(nullptr, nullptr);
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
-  if (sample) {
-    HIP_TRY(hipEventSynchronize(L->ev1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, L->ev0, L->ev1));
-    L->prof_ms[kind] += ms;
-    L->prof_sampled[kind] += 1;
+  const int slot = L->prof_open;
+  L->prof_slot_n[slot] += 1;
+  if (L->prof_slot_n[slot] >= L->prof_every || remaining <= 1) {  // close the block
+    HIP_TRY(hipEventRecord(L->prof_ev[slot][1], L->stream));
+    L->prof_slot_kind[slot] = L->prof_open_kind;
+    L->prof_open = -1;
+    L->prof_open_kind = -1;
   }
   return HLBM_OK;
 }
@@ -298,8 +343,11 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
   if ((s = ensure_partials(L, 2 * n_blocks(L) + 8)) != HLBM_OK) return bail(s);
   if (hipHostMalloc((void**)&L->red_host, 4 * sizeof(double)) != hipSuccess)
     return bail(fail(HLBM_E_OOM, "pinned host allocation failed"));
-  if (hipEventCreate(&L->ev0) != hipSuccess || hipEventCreate(&L->ev1) != hipSuccess)
-    return bail(fail(HLBM_E_DEVICE, "event creation failed"));
+  for (int i = 0; i < hlbm_lattice_s::kProfSlots; ++i) {
+    L->prof_slot_kind[i] = -1;
+    if (hipEventCreate(&L->prof_ev[i][0]) != hipSuccess || hipEventCreate(&L->prof_ev[i][1]) != hipSuccess)
+      return bail(fail(HLBM_E_DEVICE, "event creation failed"));
+  }
   if (hipMemsetAsync(L->ghost, 0, L->ssize * L->q * L->gplane, L->stream) != hipSuccess)
     return bail(fail(HLBM_E_DEVICE, "memset failed"));
   // d = 1 everywhere: a cylinder of negative diameter leaves chi = 0
@@ -320,8 +368,9 @@ void hlbm_destroy(hlbm_lattice L) {
                   L->tan_v, L->tan_rec};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
-  if (L->ev0) (void)hipEventDestroy(L->ev0);
-  if (L->ev1) (void)hipEventDestroy(L->ev1);
+  for (int i = 0; i < hlbm_lattice_s::kProfSlots; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (L->prof_ev[i][j]) (void)hipEventDestroy(L->prof_ev[i][j]);
   delete L;
 }
 
@@ -505,9 +554,14 @@ hlbm_status hlbm_window_count(hlbm_lattice L, int64_t* samples) {
 hlbm_status hlbm_profile_enable(hlbm_lattice L, int32_t every) {
   CHECK_LAT(L);
   if (every < 0) return fail(HLBM_E_INVALID, "every must be >= 0");
+  // drop what is pending: an open block is closed at its next launch only,
+  // so discard it and every recorded block
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  for (int i = 0; i < hlbm_lattice_s::kProfSlots; ++i) L->prof_slot_kind[i] = -1;
+  L->prof_open = -1;
+  L->prof_open_kind = -1;
   L->prof_every = every;
   for (int k = 0; k < 3; ++k) {
-    L->prof_count[k] = 0;
     L->prof_sampled[k] = 0;
     L->prof_ms[k] = 0.0;
   }
@@ -517,6 +571,8 @@ hlbm_status hlbm_profile_enable(hlbm_lattice L, int32_t every) {
 hlbm_status hlbm_profile_get(hlbm_lattice L, int32_t kind, double* mean_us, int64_t* sampled) {
   CHECK_LAT(L);
   if (kind < 0 || kind > 2) return fail(HLBM_E_INVALID, "kind must be 0, 1 or 2");
+  hlbm_status s = prof_collect_all(L);
+  if (s != HLBM_OK) return s;
   const int64_t n = L->prof_sampled[kind];
   if (mean_us) *mean_us = n ? 1e3 * L->prof_ms[kind] / (double)n : 0.0;
   if (sampled) *sampled = n;
@@ -596,7 +652,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     int64_t chunk = n_steps - done;
     if (steady_tol > 0.0 && chunk > check_every) chunk = check_every;
     for (int64_t k = 0; k < chunk; ++k) {
-      s = timed_launch(L, accumulate ? 1 : 0,
+      s = timed_launch(L, accumulate ? 1 : 0, chunk - k,
                        [&](hipEvent_t a, hipEvent_t b) { return launch_primal_step(L, accumulate, a, b); });
       if (s != HLBM_OK) return s;
       L->parity ^= 1;
@@ -759,7 +815,7 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
     int64_t chunk = iters - done;
     if (o->tol > 0.0 && chunk > M) chunk = M;
     for (int64_t k = 0; k < chunk; ++k) {
-      s = timed_launch(L, 2, [&](hipEvent_t a, hipEvent_t b) { return launch_adjoint_step(L, a, b); });
+      s = timed_launch(L, 2, chunk - k, [&](hipEvent_t a, hipEvent_t b) { return launch_adjoint_step(L, a, b); });
       if (s != HLBM_OK) return s;
       L->pvcur ^= 1;
       L->adj_iters += 1;

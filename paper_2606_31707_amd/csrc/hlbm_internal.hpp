@@ -66,12 +66,20 @@ struct hlbm_lattice_s {
   double* usnap = nullptr;    // dim * plane steady-check snapshot
   int usnap_valid = 0;
 
-  // profiling: one launch in prof_every of each kind is timed by events
+  // profiling: launches of each sweep kind timed in blocks of up to
+  // prof_every back-to-back launches, by events recorded on the stream
+  // before the first and after the last launch of a block; a ring of event
+  // pairs is read back lazily, so timing adds no host synchronization
+  static constexpr int kProfSlots = 64;
   int64_t prof_every = 0;
-  int64_t prof_count[3] = {0, 0, 0};   // launches seen per kind
-  int64_t prof_sampled[3] = {0, 0, 0};
+  int64_t prof_sampled[3] = {0, 0, 0};  // launches timed per kind
   double prof_ms[3] = {0.0, 0.0, 0.0};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t prof_ev[kProfSlots][2] = {};
+  int prof_slot_kind[kProfSlots] = {};     // -1: free
+  int64_t prof_slot_n[kProfSlots] = {};    // launches in the slot's block
+  int prof_next = 0;                       // next slot of the ring
+  int prof_open = -1;                      // slot of the open block, -1: none
+  int prof_open_kind = -1;
 
   // forward tangent (FP64): fdot in the AA layout, its outlet buffer, v,
   // and the device record of (J, dJ/dd . v)

@@ -339,32 +339,66 @@ __device__ void mea_terms(const Geo& g, const ObjBox& ob, int x, int y, int z, i
   out[Coef<Q>::J] = J;
 }
 
+// Neighbour (x + dx, y + dy, z + dz) of a lattice cell, dx, dy, dz in
+// {-1, 0, 1} (compile-time after unrolling): wraps the periodic axes, flags a
+// wall crossing (halfway bounce-back, which takes precedence) and an exit
+// through the inlet/outlet ends of the x axis.  The same classification as
+// classify(), written with selects and skipping the unchanged axes, so that
+// the nine pulls and pushes of a boundary cell stay short and their loads
+// issue back to back.
+__device__ __forceinline__ void neighbour(const Geo& g, int dx, int dy, int dz, int& x, int& y, int& z,
+                                          bool& bounce, bool& leaves) {
+  bounce = false;
+  leaves = false;
+  if (dy != 0) {
+    y += dy;
+    const bool o = (y < 0) | (y >= g.ny), per = g.bcy == BC_PERIODIC;
+    y += (o & per) ? (y < 0 ? g.ny : -g.ny) : 0;
+    bounce = o & !per;
+  }
+  if (dz != 0) {
+    z += dz;
+    const bool o = (z < 0) | (z >= g.nz), per = g.bcz == BC_PERIODIC;
+    z += (o & per) ? (z < 0 ? g.nz : -g.nz) : 0;
+    bounce = bounce | (o & !per);
+  }
+  if (dx != 0) {
+    x += dx;
+    const bool o = (x < 0) | (x >= g.nx), per = g.bcx == BC_PERIODIC, walls = g.bcx == BC_WALLS;
+    x += (o & per) ? (x < 0 ? g.nx : -g.nx) : 0;
+    leaves = o & !per & !walls & !bounce;
+    bounce = bounce | (o & walls);
+  }
+}
+
 // AA odd-step pull of direction k into cell (x, y, z): post-collision value of
 // the upstream cell (stored swapped), bounce-back from the own cell, or the
-// outlet's virtual column.
+// outlet's virtual column.  The source address is selected, then loaded.
 template <int Q, typename S, typename T>
 __device__ __forceinline__ T pull(const Geo& g, const S* __restrict__ A, const S* __restrict__ ghost,
                                   int x, int y, int z, int64_t cell, int k) {
   using L = Lat<Q>;
-  int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
-  const int t = classify(g, sx, sy, sz);
-  if (t == NB_BOUNCE) return (T)A[k * g.plane + cell];
-  if (t == NB_OUTLET) return (T)ghost[k * g.gplane + sy + (int64_t)g.ny * sz];
-  return (T)A[L::opp[k] * g.plane + cell_of(g, sx, sy, sz)];
+  int sx = x, sy = y, sz = z;
+  bool bounce, leaves;
+  neighbour(g, -L::cx[k], -L::cy[k], -L::cz[k], sx, sy, sz, bounce, leaves);
+  // leaves: the outlet's virtual column (an upstream position beyond x = nx-1)
+  const int64_t ia = bounce ? k * g.plane + cell : L::opp[k] * g.plane + cell_of(g, sx, sy, sz);
+  const S* pa = A + ia;
+  const S* pg = ghost + (k * g.gplane + sy + (int64_t)g.ny * sz);
+  return (T)*(leaves ? pg : pa);
 }
 
-// AA odd-step push of direction k from cell (x, y, z).
+// AA odd-step push of direction k from cell (x, y, z); a population that
+// leaves through the inlet or outlet end is dropped.
 template <int Q, typename S>
 __device__ __forceinline__ void push(const Geo& g, S* __restrict__ A, int x, int y, int z,
                                      int64_t cell, int k, S v) {
   using L = Lat<Q>;
-  int tx = x + L::cx[k], ty = y + L::cy[k], tz = z + L::cz[k];
-  const int t = classify(g, tx, ty, tz);
-  if (t == NB_BOUNCE)
-    A[L::opp[k] * g.plane + cell] = v;
-  else if (t == NB_CELL)
-    A[k * g.plane + cell_of(g, tx, ty, tz)] = v;
-  // NB_OUTLET / NB_DROP: the population leaves the domain
+  int tx = x, ty = y, tz = z;
+  bool bounce, leaves;
+  neighbour(g, L::cx[k], L::cy[k], L::cz[k], tx, ty, tz, bounce, leaves);
+  const int64_t ia = bounce ? L::opp[k] * g.plane + cell : k * g.plane + cell_of(g, tx, ty, tz);
+  if (!leaves) A[ia] = v;
 }
 
 // Canonical (post-stream) state of a cell for either step parity.
@@ -559,6 +593,16 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     omega = (T)1 / taue;
   }
 
+  // Objective terms of a region cell (moment form): from the pre-collision
+  // moments, evaluated after the stores so that their temporaries do not
+  // add to the collision's register budget.
+  bool in_region = false;
+  int64_t r = 0;
+  double odr = 0.0, oax = 0.0, oay = 0.0, oaz = 0.0, oP[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  (void)odr;
+  (void)oax;
+  (void)oay;
+  (void)oaz;
   if constexpr (ACC != 0) {
     at(acc.rho, c0, lo) += (double)drho;
     at(acc.j, c0, lo) += (double)jx;
@@ -569,22 +613,20 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       for (int k = 0; k < Q; ++k) at(acc.f, k * g.plane + c0, lo) += (double)s[k];
     }
     if (acc.tau) at(acc.tau, c0, lo) += (double)taue;
-    int64_t r;
-    if (ACC != 3 && region_index<Q>(ob, x, y, z, r)) {
+    if constexpr (ACC == 1 || ACC == 2) in_region = region_index<Q>(ob, x, y, z, r);
+    if (in_region) {
       double sd[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
-      double terms[Coef<Q>::N];
-      if constexpr (ACC == 2) {
+      if constexpr (ACC == 2) {  // J_MEA: linear in f, accumulated now
+        double terms[Coef<Q>::N];
         mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
-      } else {
-        double dr, ax, ay, az, P[6];
-        cell_moments<Q, double>(sd, dr, ax, ay, az);
-        neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
-        objective_terms<Q>(ob, (double)d, dr, ax, ay, az, P, terms);
-      }
 #pragma unroll
-      for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
+        for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
+      } else {  // moments of the pre-collision state; the terms follow the stores
+        cell_moments<Q, double>(sd, odr, oax, oay, oaz);
+        neq_flux<Q, double>(sd, odr, oax, oay, oaz, 1.0 / (1.0 + odr), oP);
+      }
     }
   }
 
@@ -656,6 +698,14 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
         A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
       }
+    }
+  }
+  if constexpr (ACC == 1) {
+    if (in_region) {
+      double terms[Coef<Q>::N];
+      objective_terms<Q>(ob, (double)d, odr, oax, oay, oaz, oP, terms);
+#pragma unroll
+      for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
     }
   }
 }
@@ -1698,15 +1748,13 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      int sx = x - L::cx[k], sy = y - L::cy[k], sz = z - L::cz[k];
-      const int t = classify(g, sx, sy, sz);
-      if (t == NB_BOUNCE)
-        ph[k] = A[k * g.plane + cell];
-      else if (t == NB_OUTLET)
-        ph[k] = (T)0;
-      else
-        ph[k] = A[L::opp[k] * g.plane + cell_of(g, sx, sy, sz)];
+    for (int k = 0; k < Q; ++k) {  // beyond the outlet: no adjoint inflow
+      int sx = x, sy = y, sz = z;
+      bool bounce, leaves;
+      neighbour(g, -L::cx[k], -L::cy[k], -L::cz[k], sx, sy, sz, bounce, leaves);
+      const int64_t ia = bounce ? k * g.plane + cell : L::opp[k] * g.plane + cell_of(g, sx, sy, sz);
+      const T v = A[leaves ? k * g.plane + cell : ia];
+      ph[k] = leaves ? (T)0 : v;
     }
   }
   T lam[Q];

@@ -344,7 +344,8 @@ class Lattice:
         _check(self._lib.hlbm_synchronize(self._h))
 
     def profile_enable(self, every=1):
-        """Times one launch in `every` of each sweep kind with HIP events (0: off)."""
+        """Times the sweeps of each kind in blocks of up to `every` back-to-back launches with
+        HIP events recorded on the stream (0: off); see profile()."""
         _check(self._lib.hlbm_profile_enable(self._h, int(every)))
 
     def profile(self):
