@@ -123,6 +123,108 @@ def cpu_baseline(w: I.Workload, primal_steps: int, adj_iters: int):
                       f"preparation, {adj_iters} adjoint iterations and the gradient ({dt:.1f} s of CPU)"}
 
 
+ORACLE_CASES = {
+    # name: (workload, primal steps, adjoint iterations) for the all-core run;
+    # the single-thread run takes 1/10 of them (at least one)
+    "channel_re20": (I.channel_re20, 4000, 20000),
+    "vortex_re100": (I.vortex_re100, 1000, 200),
+    "les_re3900": (I.les_re3900, 20, 0),     # the oracle's dense per-cell adjoint Jacobians need 218 GB here
+    "autograd_re40": (I.autograd_re40, 4000, 2000),
+}
+
+
+def oracle_worker(case: str, primal: int, adj: int):
+    """One oracle timing in this process (thread count from OMP_NUM_THREADS):
+    primal steps, then the steady adjoint's preparation and iterations."""
+    import oracle as O
+    w = ORACLE_CASES[case][0]()
+    p = O.Params(stencil=w.stencil, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs, bc_x=O.BC_INLET_OUTLET,
+                 bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile, u_in=w.u_max)
+    L = O.Lattice(p)
+    L.build_cylinder(w.xc, w.yc, w.D, noise=I.porosity_noise(w), noise_mode=w.noise_mode, box_half=w.box_half)
+    L.init_equilibrium(1.0, I.initial_velocity(w))
+    L.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
+    t0 = time.perf_counter()
+    L.step(primal)
+    tp = time.perf_counter() - t0
+    out = {"case": case, "cells": w.n, "primal_steps": primal, "primal_s": tp,
+           "primal_MLUPS": primal * w.n / tp / 1e6}
+    if adj > 0:
+        t0 = time.perf_counter()
+        L.adjoint_prepare(0)
+        tprep = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        L.adjoint_iterate(adj)
+        ta = time.perf_counter() - t0
+        out.update({"adjoint_prepare_s": tprep, "adjoint_iters": adj, "adjoint_s": ta,
+                    "adjoint_MLUPS": adj * w.n / ta / 1e6})
+    print(json.dumps(out), flush=True)
+
+
+def gpu_rates(case: str, precision: int, primal: int, adj: int):
+    """The library on the same workload: back-to-back primal steps and steady
+    adjoint iterations, wall time per launch."""
+    w = ORACLE_CASES[case][0]()
+    G = H.Lattice(stencil=w.stencil, precision=precision, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
+                  bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
+                  u_in=w.u_max)
+    G.build_cylinder(w.xc, w.yc, w.D, noise=I.porosity_noise(w), noise_mode=w.noise_mode,
+                     box_half=w.box_half)
+    G.init_equilibrium(1.0, I.initial_velocity(w))
+    G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
+    G.run_primal(20)
+    G.synchronize()
+    t0 = time.perf_counter()
+    G.run_primal(primal)
+    G.synchronize()
+    tp = time.perf_counter() - t0
+    G.solve_adjoint(H.SOURCE_STEADY, max_iters=20, turb=H.TURB_FROZEN)
+    G.synchronize()
+    t0 = time.perf_counter()
+    G.solve_adjoint(H.SOURCE_STEADY, max_iters=adj, turb=H.TURB_FROZEN, restart=False)
+    G.synchronize()
+    ta = time.perf_counter() - t0
+    G.close()
+    return {"primal_MLUPS": primal * w.n / tp / 1e6, "adjoint_MLUPS": adj * w.n / ta / 1e6}
+
+
+def report_oracle(all_threads: int):
+    """The oracle timed beside the GPU: single-thread and all-core FP64
+    oracle MLUPS (separate processes, OMP_NUM_THREADS 1 and all), and the
+    library's FP64 (and, for the LES lattice, FP32) rates on the same inputs."""
+    import subprocess
+    rows = []
+    for case, (wf, primal, adj) in ORACLE_CASES.items():
+        row = {"case": case, "workload": wf().name}
+        for threads, scale in ((1, 10), (all_threads, 1)):
+            np_, na = max(1, primal // scale), (max(1, adj // scale) if adj else 0)
+            env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-worker", case,
+                                str(np_), str(na)], env=env, capture_output=True, text=True, check=True)
+            rec = json.loads(r.stdout.strip().splitlines()[-1])
+            rec["threads"] = threads
+            row["oracle_1_thread" if threads == 1 else "oracle_all_threads"] = rec
+            log(f"oracle {case} x{threads}: primal {rec['primal_MLUPS']:.2f} MLUPS"
+                + (f", adjoint {rec['adjoint_MLUPS']:.2f} MLUPS" if adj else ""))
+        gp = 4000 if wf().n < 10 ** 6 else 100
+        row["gpu_fp64"] = gpu_rates(case, H.FP64, gp, gp)
+        if wf().stencil == I.D3Q19:
+            row["gpu_fp32"] = gpu_rates(case, H.FP32, gp, gp)
+        log(f"gpu {case}: {row['gpu_fp64']}")
+        rows.append(row)
+    import platform
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    print(json.dumps({"report": "oracle beside the GPU", "host_cpu": cpu, "host_threads": all_threads,
+                      "machine": platform.machine(), "cases": rows}), flush=True)
+
+
 def kernel_source_hash() -> str:
     """SHA-256 over the device code and its build flags (the counters are
     tied to them)."""
@@ -611,7 +713,7 @@ def main():
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d", "tangent"],
+    ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d", "tangent", "oracle"],
                     default=None,
                     help="print a secondary measurement report instead of the benchmark line")
     ap.add_argument("--fields", type=int, default=32)
@@ -634,14 +736,24 @@ def main():
     ap.add_argument("--mem-cap-gib", type=float, default=1.0)
     ap.add_argument("--tick", type=int, default=256)
     ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--oracle-threads", type=int, default=0, help="all-core thread count (0: the host's)")
+    ap.add_argument("--oracle-worker", nargs=3, default=None, metavar=("CASE", "PRIMAL", "ADJ"),
+                    help=argparse.SUPPRESS)
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
                     help="write the profiles/ summaries from the rocprofv3 output under DIR and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
+    if args.oracle_worker:
+        oracle_worker(args.oracle_worker[0], int(args.oracle_worker[1]), int(args.oracle_worker[2]))
+        return
     if args.profile_summary:
         summarize_profiles(args.profile_summary)
+        return
+    if args.report == "oracle":
+        threads = args.oracle_threads or int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+        report_oracle(threads)
         return
     if args.report == "differentiation":
         report_differentiation(args.fields, args.fd_fields, args.fd_directions)
