@@ -22,10 +22,12 @@ enum { NB_CELL = 0, NB_BOUNCE = 1, NB_OUTLET = 2, NB_DROP = 3 };
 #ifndef HLBM_XCD_REMAP
 #define HLBM_XCD_REMAP 1
 #endif
-// 128 x 2 tiles: measured best for the FP64 sweeps (within 2-3 % of 64 x 4 and
-// 256 x 1 for every stencil and precision).
+// BX x BY tiles: the cell grid of the set-up, gather and reduction kernels
+// and the per-member tiles of the packed launches; the sweeps proper take
+// runs of SWEEP_BLOCK consecutive cells (see sweep_cell).
 constexpr int BX = HLBM_TILE_BX;   // wavefronts along x: BX consecutive cells per row
 constexpr int BY = 256 / BX;       // rows per 256-thread workgroup
+constexpr int SWEEP_BLOCK = 256;   // consecutive cells per workgroup of the sweeps
 constexpr int NXCD = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 
 // ---- velocity sets (Sec. 2.1: D2Q9 and D3Q19) ------------------------------

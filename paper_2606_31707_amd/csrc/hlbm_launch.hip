@@ -72,9 +72,15 @@ dim3 cell_grid(const hlbm_lattice_s* L) {
 }
 
 static const dim3 kBlock(BX, BY, 1);
+static const dim3 kSweepBlock(SWEEP_BLOCK, 1, 1);
 
-// 1D grid of the sweep kernels (k_primal, k_adjoint): one workgroup per tile.
+// 1D grids of the sweep kernels: runs of SWEEP_BLOCK consecutive cells
+// (plain primal steps, tangent) or one workgroup per BX x BY tile (window
+// steps, adjoint); see the sweep prologues.
 static dim3 sweep_grid(const hlbm_lattice_s* L) {
+  return dim3((unsigned)((L->n + SWEEP_BLOCK - 1) / SWEEP_BLOCK), 1, 1);
+}
+static dim3 tile_grid(const hlbm_lattice_s* L) {
   const dim3 c = cell_grid(L);
   return dim3(c.x * c.y * c.z, 1, 1);
 }
@@ -93,11 +99,12 @@ static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
   S* A = (S*)L->f;
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
-  const dim3 grid = sweep_grid(L);
+  const dim3 grid = ACC == 0 ? sweep_grid(L) : tile_grid(L);
+  const dim3 block = ACC == 0 ? kSweepBlock : kBlock;
   if (L->parity == 0)
-    launch_k(k_primal<Q, S, false, ACC, HRR>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    launch_k(k_primal<Q, S, false, ACC, HRR>, grid, block, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
   else
-    launch_k(k_primal<Q, S, true, ACC, HRR>, grid, kBlock, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    launch_k(k_primal<Q, S, true, ACC, HRR>, grid, block, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
 }
 
 // Window steps: the objective terms are fused into the sweep when the
@@ -211,14 +218,14 @@ hipError_t launch_tangent_step(hlbm_lattice_s* L) {
   const bool odd = L->parity != 0;
   if (L->desc.stencil == HLBM_D2Q9) {
     if (odd)
-      k_tangent<9, true><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+      k_tangent<9, true><<<grid, kSweepBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
     else
-      k_tangent<9, false><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+      k_tangent<9, false><<<grid, kSweepBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
   } else {
     if (odd)
-      k_tangent<19, true><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+      k_tangent<19, true><<<grid, kSweepBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
     else
-      k_tangent<19, false><<<grid, kBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
+      k_tangent<19, false><<<grid, kSweepBlock, 0, L->stream>>>(g, c, A, L->tan_f, dp, L->tan_v, gh, L->tan_ghost);
   }
   return hipGetLastError();
 }
@@ -377,7 +384,7 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   const SA* prep = (const SA*)L->prep;
   const bool odd = (L->adj_iters & 1) != 0;
   const bool hrr = L->desc.collision == HLBM_COLL_HRR, mea = L->obj_kind == HLBM_OBJ_MEA;
-  const dim3 grid = sweep_grid(L);
+  const dim3 grid = tile_grid(L);
 #define HLBM_ADJ(ODD, HRR, MEA)                                                                        \
   launch_k(k_adjoint<Q, SA, ODD, HRR, MEA>, grid, kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src, \
            L->oprep, pin, pout)
