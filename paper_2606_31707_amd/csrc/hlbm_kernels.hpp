@@ -583,21 +583,29 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   using T = typename Prec<S>::T;
   const int64_t cell = c0 + lo;
   const bool inout = (g.bcx == BC_INOUT);
+  // The pinned inlet (x = 0: equilibrium inflow, not collided, a source only)
+  // and the outlet (x = nx-1) of an inlet/outlet channel.
+  const bool inlet = inout && x == 0, outlet = inout && (x == g.nx - 1);
+  // Fast lanes: every lane of the even step; in the odd step the cells whose
+  // neighbours are ordinary cells except across the inlet and outlet ends,
+  // i.e. the interior cells plus the inlet and outlet cells of rows away from
+  // walls and periodic seams.  They run one instruction stream (the inlet and
+  // outlet only switch a few loads and stores), so a wavefront that holds a
+  // row end does not run a second, generic path for it.
+  bool fast = true;
+  if constexpr (ODD) {
+    const bool rows = y > 0 && y < g.ny - 1 && (L::D == 2 || (z > 0 && z < g.nz - 1));
+    fast = rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
+  }
   T s[Q];
-  if (inout && x == 0) {  // pinned equilibrium inlet: not collided, source only
+  if (inlet && !fast) {  // odd step, inlet cell of a wall row: pinned, pushed
     inlet_state<Q, T>(g, y, s);
-    if (!ODD) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) A[L::opp[k] * g.plane + cell] = (S)s[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
-    }
+    for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
     return;
   }
   // Porosity and populations are requested together.
   const T d = (T)at(dpor, c0, lo);
-  const bool interior = ODD && interior_cell<Q>(g, x, y, z);
   // All population loads are issued before any arithmetic on them (the
   // scheduler otherwise interleaves early sums, which forces a wait for the
   // first loads before the remaining ones are even issued).
@@ -605,22 +613,29 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream(&at(A, k * g.plane + c0, lo));
     __builtin_amdgcn_sched_barrier(0);
-  } else if (interior) {
+  } else if (fast) {
+    if (!inlet) {  // the inlet's upstream lies outside the lattice
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      s[k] = (T)ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] == -1 && outlet)  // upstream (nx, y - cy, z - cz): the virtual column
+          s[k] = (T)ghost[k * g.gplane + (y - L::cy[k]) + (int64_t)g.ny * (z - L::cz[k])];
+        else
+          s[k] = (T)ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = pull<Q, S, T>(g, A, ghost, x, y, z, cell, k);
   }
+  if (inlet) inlet_state<Q, T>(g, y, s);
 
   T drho, jx, jy, jz;
   cell_moments<Q, T>(s, drho, jx, jy, jz);
   const T rho = (T)1 + drho;
   const T ir = recip(rho);
 
-  if (cell == c.probe_cell) *c.probe_out = (double)(jy * ir);
+  if (cell == c.probe_cell && !inlet) *c.probe_out = (double)(jy * ir);
   T omega = (T)c.omega0;
   T taue = (T)c.tau0;
   if (c.smag) {
@@ -641,7 +656,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   (void)oax;
   (void)oay;
   (void)oaz;
-  if constexpr (ACC != 0) {
+  if (ACC != 0 && !inlet) {  // the pinned inlet is not part of the window
     at(acc.rho, c0, lo) += (double)drho;
     at(acc.j, c0, lo) += (double)jx;
     at(acc.j, g.plane + c0, lo) += (double)jy;
@@ -668,7 +683,6 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
   }
 
-  const bool outlet = inout && (x == g.nx - 1);
   if constexpr (HRR) {
     hrr_collide<Q, T>(s, drho, jx, jy, jz, d, omega, c.force);
   } else {
@@ -703,6 +717,8 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
   }
 
+  if (inlet) inlet_state<Q, T>(g, y, s);  // pinned: not collided
+
   if (!ODD) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) st_stream(&at(A, L::opp[k] * g.plane + c0, lo), (S)s[k]);
@@ -717,13 +733,18 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         ghost[k * g.gplane + y + (int64_t)g.ny * z] = (S)vs;
       }
     }
-  } else if (interior) {
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
   } else {
+    if (fast) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+      for (int k = 0; k < Q; ++k) {
+        // populations leaving through the inlet or outlet end are dropped
+        if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
+        st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+    }
     if (outlet) {
       const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
       const T uu = ux * ux + uy * uy + uz * uz;
