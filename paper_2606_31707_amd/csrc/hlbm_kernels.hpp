@@ -1789,27 +1789,37 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   constexpr int D = L::D;
   const int64_t cell = c0 + lo;
   const bool inout = (g.bcx == BC_INOUT);
-  if (inout && x == 0) {  // inlet: no dependence on the state, lambda = 0
-    if (!ODD) {
+  // inlet: no dependence on the state, lambda = 0; outlet: no adjoint inflow
+  // from beyond x = nx-1.  As in the primal sweep, the inlet and outlet cells
+  // of rows away from walls and periodic seams share the interior path of
+  // the odd step (fast lanes).
+  const bool inlet = inout && x == 0, outlet = inout && (x == g.nx - 1);
+  bool fast = true;
+  if constexpr (ODD) {
+    const bool rows = y > 0 && y < g.ny - 1 && (D == 2 || (z > 0 && z < g.nz - 1));
+    fast = rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
+  }
+  if (inlet && !fast) {  // odd step, inlet cell of a wall row
 #pragma unroll
-      for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (SA)0;
-    } else {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, (SA)0);
-    }
+    for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, (SA)0);
     return;
   }
-  const bool outlet = inout && (x == g.nx - 1);
   T ph[Q];  // phihat_k = phi_opp(k)
-  const bool interior = ODD && interior_cell<Q>(g, x, y, z);
   if (!ODD) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&at(A, k * g.plane + c0, lo));
     __builtin_amdgcn_sched_barrier(0);
     if (outlet) adjoint_zero_outlet<Q, SA>(g, x, y, z, ph);
-  } else if (interior) {
+  } else if (fast) {
+    if (!inlet) {  // the inlet's upstream lies outside the lattice
 #pragma unroll
-    for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+      for (int k = 0; k < Q; ++k) {
+        if (L::cx[k] == -1 && outlet)
+          ph[k] = (T)0;
+        else
+          ph[k] = ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
@@ -1821,6 +1831,10 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
       const T v = A[leaves ? k * g.plane + cell : ia];
       ph[k] = leaves ? (T)0 : v;
     }
+  }
+  if (inlet) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ph[k] = (T)0;
   }
   T lam[Q];
   if constexpr (HRR) {
@@ -1953,12 +1967,21 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     }
   }
 
+  if (inlet) {  // lambda = 0 at the pinned inlet
+#pragma unroll
+    for (int k = 0; k < Q; ++k) lam[k] = (T)0;
+  }
+
   if (!ODD) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) st_stream(&at(A, i * g.plane + c0, lo), lam[i]);
-  } else if (interior) {
+  } else if (fast) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), lam[L::opp[k]]);
+    for (int k = 0; k < Q; ++k) {
+      // values leaving through the inlet or outlet end are dropped
+      if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
+      st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), lam[L::opp[k]]);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, lam[L::opp[k]]);
