@@ -628,7 +628,10 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = pull<Q, S, T>(g, A, ghost, x, y, z, cell, k);
   }
-  if (inlet) inlet_state<Q, T>(g, y, s);
+  if (ODD && inlet) {  // loaded nothing; its update is replaced by the pinned values below
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s[k] = (T)0;
+  }
 
   T drho, jx, jy, jz;
   cell_moments<Q, T>(s, drho, jx, jy, jz);
