@@ -233,7 +233,7 @@ hlbm_status prof_collect_all(hlbm_lattice_s* L) {
 template <typename F>
 hlbm_status timed_launch(hlbm_lattice_s* L, int kind, int64_t remaining, F&& launch) {
   if (L->prof_every <= 0) {
-    hipError_t e = launch(nullptr, nullptr);
+    hipError_t e = launch();
     if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
     return HLBM_OK;
   }
@@ -252,7 +252,7 @@ hlbm_status timed_launch(hlbm_lattice_s* L, int kind, int64_t remaining, F&& lau
     L->prof_open_kind = kind;
     L->prof_slot_n[slot] = 0;
   }
-  hipError_t e = launch(nullptr, nullptr);
+  hipError_t e = launch();
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "sweep launch: %s", hipGetErrorString(e));
   const int slot = L->prof_open;
   L->prof_slot_n[slot] += 1;
@@ -653,7 +653,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     if (steady_tol > 0.0 && chunk > check_every) chunk = check_every;
     for (int64_t k = 0; k < chunk; ++k) {
       s = timed_launch(L, accumulate ? 1 : 0, chunk - k,
-                       [&](hipEvent_t a, hipEvent_t b) { return launch_primal_step(L, accumulate, a, b); });
+                       [&]() { return launch_primal_step(L, accumulate); });
       if (s != HLBM_OK) return s;
       L->parity ^= 1;
       L->steps += 1;
@@ -815,7 +815,7 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
     int64_t chunk = iters - done;
     if (o->tol > 0.0 && chunk > M) chunk = M;
     for (int64_t k = 0; k < chunk; ++k) {
-      s = timed_launch(L, 2, chunk - k, [&](hipEvent_t a, hipEvent_t b) { return launch_adjoint_step(L, a, b); });
+      s = timed_launch(L, 2, chunk - k, [&]() { return launch_adjoint_step(L); });
       if (s != HLBM_OK) return s;
       L->pvcur ^= 1;
       L->adj_iters += 1;

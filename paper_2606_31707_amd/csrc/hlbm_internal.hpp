@@ -136,8 +136,7 @@ hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_
 hipError_t launch_mea_flags(hlbm_lattice_s* L);
 hipError_t launch_tangent_step(hlbm_lattice_s* L);
 hipError_t launch_tangent_objective(hlbm_lattice_s* L, double* partials, int* nblocks);
-hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0 = nullptr,
-                              hipEvent_t e1 = nullptr);
+hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate);
 hipError_t launch_gather(hlbm_lattice_s* L, double* out_dev);
 hipError_t launch_scatter(hlbm_lattice_s* L, const double* in_dev);
 hipError_t launch_moments(hlbm_lattice_s* L, double* rho_dev, double* u_dev);
@@ -147,7 +146,7 @@ hipError_t launch_objective(hlbm_lattice_s* L, int which, double* partials, int*
 hipError_t launch_finalize_sum(hlbm_lattice_s* L, const double* partials, int n, double* out);
 hipError_t launch_finalize_max2(hlbm_lattice_s* L, const double* partials, int n, double* out);
 hipError_t launch_adjoint_prep(hlbm_lattice_s* L, int source, double tau_adj, int turb);
-hipError_t launch_adjoint_step(hlbm_lattice_s* L, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_adjoint_step(hlbm_lattice_s* L);
 hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partials, int* nblocks);
 hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev);
 hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev);

@@ -307,6 +307,19 @@ __device__ __forceinline__ bool region_index(const ObjBox& ob, int x, int y, int
   return true;
 }
 
+// acc[m * stride + r] += v[m], m < N.  Every old value is read before any is
+// written back: the compiler has to assume that the slots may alias, so
+// updates written one after the other would each wait for a memory round
+// trip.
+template <int N>
+__device__ __forceinline__ void accumulate_terms(double* acc, int64_t stride, int64_t r, const double (&v)[N]) {
+  double o[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) o[m] = acc[m * stride + r];
+#pragma unroll
+  for (int m = 0; m < N; ++m) acc[m * stride + r] = o[m] + v[m];
+}
+
 // ---- J_MEA, the momentum-exchange drag (Sec. 4, Eq. obj_mea) -------------
 // J = (1/A) sum_{x in surface} sum_i xi_i,x (f_i(x + xi_i) - f_opp(i)(x)) is
 // linear in f.  Collected by the slot each term reads it is
@@ -327,16 +340,22 @@ __device__ __forceinline__ double mea_g(const Geo& g, const ObjBox& ob, int x, i
 
 // Region-cell terms of J_MEA from the shifted state sd (only J is nonzero).
 template <int Q>
-__device__ void mea_terms(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
-                          const double (&sd)[Q], double* out) {
+__device__ __forceinline__ double mea_value(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
+                                            const double (&sd)[Q]) {
   using L = Lat<Q>;
-#pragma unroll
-  for (int m = 0; m < Coef<Q>::N; ++m) out[m] = 0.0;
   double J = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     if (L::cx[k] != 0) J += mea_g<Q>(g, ob, x, y, z, r, k) * (sd[k] + L::w[k]);
-  out[Coef<Q>::J] = J;
+  return J;
+}
+
+template <int Q>
+__device__ void mea_terms(const Geo& g, const ObjBox& ob, int x, int y, int z, int64_t r,
+                          const double (&sd)[Q], double* out) {
+#pragma unroll
+  for (int m = 0; m < Coef<Q>::N; ++m) out[m] = 0.0;
+  out[Coef<Q>::J] = mea_value<Q>(g, ob, x, y, z, r, sd);
 }
 
 // Neighbour (x + dx, y + dy, z + dz) of a lattice cell, dx, dy, dz in
@@ -534,6 +553,7 @@ __device__ __forceinline__ bool sweep_cell(const Geo& g, uint32_t c0, uint32_t l
   const int64_t cell = tile_c0 + threadIdx.x;                                 \
   const bool inout = (g.bcx == BC_INOUT);                                     \
   (void)inout;                                                                \
+  (void)tile_lo;                                                              \
   (void)cell;
 
 #define SWEEP_PROLOGUE_TILES                                                 \
@@ -606,6 +626,15 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
   // Porosity and populations are requested together.
   const T d = (T)at(dpor, c0, lo);
+  // Window sums of rho and j: their old values are requested with the
+  // populations (and all of them before any is written back, see
+  // accumulate_terms).  The inlet's slots are read but not updated.
+  double wold[L::D + 1];
+  if constexpr (ACC != 0) {
+    wold[0] = at(acc.rho, c0, lo);
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) wold[1 + a] = at(acc.j, a * g.plane + c0, lo);
+  }
   // All population loads are issued before any arithmetic on them (the
   // scheduler otherwise interleaves early sums, which forces a wait for the
   // first loads before the remaining ones are even issued).
@@ -655,18 +684,28 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   bool in_region = false;
   int64_t r = 0;
   double odr = 0.0, oax = 0.0, oay = 0.0, oaz = 0.0, oP[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double omea = 0.0;  // J_MEA of the cell
+  (void)omea;
   (void)odr;
   (void)oax;
   (void)oay;
   (void)oaz;
   if (ACC != 0 && !inlet) {  // the pinned inlet is not part of the window
-    at(acc.rho, c0, lo) += (double)drho;
-    at(acc.j, c0, lo) += (double)jx;
-    at(acc.j, g.plane + c0, lo) += (double)jy;
-    if (L::D == 3) at(acc.j, 2 * g.plane + c0, lo) += (double)jz;
-    if (acc.f) {
+    at(acc.rho, c0, lo) = wold[0] + (double)drho;
+    at(acc.j, c0, lo) = wold[1] + (double)jx;
+    at(acc.j, g.plane + c0, lo) = wold[2] + (double)jy;
+    if constexpr (L::D == 3) at(acc.j, 2 * g.plane + c0, lo) = wold[3] + (double)jz;
+    if (acc.f) {  // in groups of 4 (read, then write back)
 #pragma unroll
-      for (int k = 0; k < Q; ++k) at(acc.f, k * g.plane + c0, lo) += (double)s[k];
+      for (int k0 = 0; k0 < Q; k0 += 4) {
+        double o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (k0 + i < Q) o[i] = at(acc.f, (k0 + i) * g.plane + c0, lo);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (k0 + i < Q) at(acc.f, (k0 + i) * g.plane + c0, lo) = o[i] + (double)s[k0 + i];
+      }
     }
     if (acc.tau) at(acc.tau, c0, lo) += (double)taue;
     if constexpr (ACC == 1 || ACC == 2) in_region = region_index<Q>(ob, x, y, z, r);
@@ -674,11 +713,8 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       double sd[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) sd[k] = (double)s[k];
-      if constexpr (ACC == 2) {  // J_MEA: linear in f, accumulated now
-        double terms[Coef<Q>::N];
-        mea_terms<Q>(g, ob, x, y, z, r, sd, terms);
-#pragma unroll
-        for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
+      if constexpr (ACC == 2) {  // J_MEA (linear in f): only its J term is nonzero
+        omea = mea_value<Q>(g, ob, x, y, z, r, sd);
       } else {  // moments of the pre-collision state; the terms follow the stores
         cell_moments<Q, double>(sd, odr, oax, oay, oaz);
         neq_flux<Q, double>(sd, odr, oax, oay, oaz, 1.0 / (1.0 + odr), oP);
@@ -766,9 +802,11 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     if (in_region) {
       double terms[Coef<Q>::N];
       objective_terms<Q>(ob, (double)d, odr, oax, oay, oaz, oP, terms);
-#pragma unroll
-      for (int m = 0; m < Coef<Q>::N; ++m) acc.obj[m * ob.rplane + r] += terms[m];
+      accumulate_terms<Coef<Q>::N>(acc.obj, ob.rplane, r, terms);
     }
+  }
+  if constexpr (ACC == 2) {
+    if (in_region) acc.obj[Coef<Q>::J * ob.rplane + r] += omea;
   }
 }
 
@@ -1003,8 +1041,7 @@ __global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox
     neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
     objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
   }
-#pragma unroll
-  for (int m = 0; m < Coef<Q>::N; ++m) acc_obj[m * ob.rplane + r] += terms[m];
+  accumulate_terms<Coef<Q>::N>(acc_obj, ob.rplane, r, terms);
 }
 
 // Packed launch: one workgroup grid covering several lattices of one stencil
@@ -1807,6 +1844,20 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     for (int k = 0; k < Q; ++k) push<Q, SA>(g, A, x, y, z, cell, k, (SA)0);
     return;
   }
+  // Frozen data of the BGK adjoint, requested before phi: the inlet and
+  // outlet overrides of phi below have to wait for its loads, so a load
+  // issued after them would start a second memory round trip.
+  T tx = (T)0, ty = (T)0, tz = (T)0, d = (T)0, omega = (T)0;
+  if constexpr (!HRR) {
+    tx = at(prep, c0, lo);
+    ty = at(prep, g.plane + c0, lo);
+    if constexpr (D == 3) tz = at(prep, 2 * g.plane + c0, lo);
+    d = at(prep, D * g.plane + c0, lo);
+    // per-cell omega (LES): plane D + 1; otherwise the load repeats d's
+    // (no branch between the loads) and the constant is taken
+    const T om = at(prep, (ac.les ? D + 1 : D) * g.plane + c0, lo);
+    omega = ac.les ? om : (T)ac.omega0;
+  }
   T ph[Q];  // phihat_k = phi_opp(k)
   if (!ODD) {
 #pragma unroll
@@ -1843,12 +1894,6 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   if constexpr (HRR) {
     hrr_adjoint<Q, T>(ph, prep, g.plane, cell, ac.diff != 0, lam);
   } else {
-    // Frozen data first, so that its loads overlap the moments.
-    const T tx = at(prep, c0, lo);
-    const T ty = at(prep, g.plane + c0, lo);
-    const T tz = (D == 3) ? (T)at(prep, 2 * g.plane + c0, lo) : (T)0;
-    const T d = at(prep, D * g.plane + c0, lo);
-    const T omega = ac.les ? (T)at(prep, (D + 1) * g.plane + c0, lo) : (T)ac.omega0;
     // Weighted moments of phi (phi_i = ph[opp i], xi_opp(k) = -xi_k) over the
     // opposite pairs: m0 = sum w phi, m1 = sum w phi xi, M2 = sum w phi xi xi;
     // terms with zero lattice coefficients are never formed.

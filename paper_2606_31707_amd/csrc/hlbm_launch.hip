@@ -1,22 +1,9 @@
-// hlbm_launch.hip -- host-side launchers of the gfx950 kernels: grid shape,
-// template dispatch over stencil and precision, optional start/stop events
-// recorded at the kernel's own start and end (hipExtLaunchKernelGGL).
-#include <hip/hip_ext.h>
+// hlbm_launch.hip -- host-side launchers of the gfx950 kernels: grid shape
+// and template dispatch over stencil, precision, collision and window mode.
 
 #include "hlbm_kernels.hpp"
 
 namespace hlbm {
-
-// Launches `kernel`; with events, the runtime records e0/e1 when the kernel
-// itself starts and ends (no dispatch latency in the measurement).
-template <typename K, typename... Args>
-static void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t e0, hipEvent_t e1,
-                     Args... args) {
-  if (e0 != nullptr)
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, e0, e1, 0, args...);
-  else
-    hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
-}
 
 Geo make_geo(const hlbm_lattice_s* L) {
   Geo g;
@@ -89,7 +76,7 @@ static dim3 tile_grid(const hlbm_lattice_s* L) {
 // more registers, which would lower the occupancy of the BGK sweeps if both
 // shared one kernel.
 template <int Q, typename S, int ACC, bool HRR>
-static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
+static void primal_variant(hlbm_lattice_s* L) {
   using Dd = typename Prec<S>::Dd;
   const Geo g = make_geo(L);
   const Coll c = make_coll(L);
@@ -102,9 +89,9 @@ static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid = ACC == 0 ? sweep_grid(L) : tile_grid(L);
   const dim3 block = ACC == 0 ? kSweepBlock : kBlock;
   if (L->parity == 0)
-    launch_k(k_primal<Q, S, false, ACC, HRR>, grid, block, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    k_primal<Q, S, false, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
   else
-    launch_k(k_primal<Q, S, true, ACC, HRR>, grid, block, L->stream, e0, e1, g, c, ob, A, dp, gh, acc);
+    k_primal<Q, S, true, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
 }
 
 // Window steps: the objective terms are fused into the sweep when the
@@ -112,9 +99,9 @@ static void primal_variant(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
 // region pass (before the step, from the same pre-collision state) when it is
 // small, so that the sweep keeps the register budget of a plain step.
 template <int Q, typename S, bool HRR>
-static void primal_mode(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+static void primal_mode(hlbm_lattice_s* L, int accumulate) {
   if (!accumulate) {
-    primal_variant<Q, S, 0, HRR>(L, e0, e1);
+    primal_variant<Q, S, 0, HRR>(L);
     return;
   }
   const bool mea = L->obj_set && L->obj_kind == HLBM_OBJ_MEA;
@@ -130,20 +117,20 @@ static void primal_mode(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEve
       k_window_region<Q, S, false><<<rg, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
                                                                  (const S*)L->ghost, L->parity,
                                                                  (const Dd*)L->dpor, L->acc_obj);
-    primal_variant<Q, S, 3, HRR>(L, e0, e1);
+    primal_variant<Q, S, 3, HRR>(L);
   } else if (mea) {
-    primal_variant<Q, S, 2, HRR>(L, e0, e1);
+    primal_variant<Q, S, 2, HRR>(L);
   } else {
-    primal_variant<Q, S, 1, HRR>(L, e0, e1);
+    primal_variant<Q, S, 1, HRR>(L);
   }
 }
 
 template <int Q, typename S>
-static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate) {
   if (L->desc.collision == HLBM_COLL_HRR)
-    primal_mode<Q, S, true>(L, accumulate, e0, e1);
+    primal_mode<Q, S, true>(L, accumulate);
   else
-    primal_mode<Q, S, false>(L, accumulate, e0, e1);
+    primal_mode<Q, S, false>(L, accumulate);
   return hipGetLastError();
 }
 
@@ -161,8 +148,8 @@ static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, 
     }                                                                         \
   } while (0)
 
-hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate, hipEvent_t e0, hipEvent_t e1) {
-  HLBM_DISPATCH(L, primal_impl, L, accumulate, e0, e1);
+hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate) {
+  HLBM_DISPATCH(L, primal_impl, L, accumulate);
 }
 
 template <int Q, typename S>
@@ -370,7 +357,7 @@ hipError_t launch_adjoint_prep(hlbm_lattice_s* L, int source, double tau_adj, in
 }
 
 template <int Q, typename S>
-static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t adjoint_impl(hlbm_lattice_s* L) {
   using SA = typename AdjT<S>::type;
   AdjC ac;
   ac.les = L->adj_les;
@@ -386,8 +373,8 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
   const bool hrr = L->desc.collision == HLBM_COLL_HRR, mea = L->obj_kind == HLBM_OBJ_MEA;
   const dim3 grid = tile_grid(L);
 #define HLBM_ADJ(ODD, HRR, MEA)                                                                        \
-  launch_k(k_adjoint<Q, SA, ODD, HRR, MEA>, grid, kBlock, L->stream, e0, e1, g, ob, ac, A, prep, L->src, \
-           L->oprep, pin, pout)
+  k_adjoint<Q, SA, ODD, HRR, MEA><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, \
+                                                                   pout)
   if (hrr) {
     if (mea) {
       if (odd) HLBM_ADJ(true, true, true); else HLBM_ADJ(false, true, true);
@@ -404,8 +391,8 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) 
 #undef HLBM_ADJ
   return hipGetLastError();
 }
-hipError_t launch_adjoint_step(hlbm_lattice_s* L, hipEvent_t e0, hipEvent_t e1) {
-  HLBM_DISPATCH(L, adjoint_impl, L, e0, e1);
+hipError_t launch_adjoint_step(hlbm_lattice_s* L) {
+  HLBM_DISPATCH(L, adjoint_impl, L);
 }
 
 template <int Q, typename S>
