@@ -127,6 +127,17 @@ typedef enum {
  * closure (smagorinsky_cs > 0). */
 typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
 
+/* Cache hints of the population loads and stores of the D2Q9 BGK primal
+ * sweep (with or without the window statistics).
+ * AUTO: streaming (nontemporal) hints when the populations and the porosity
+ * exceed 256 MiB, the size of the MI355X Infinity Cache, plain accesses
+ * otherwise (a lattice that stays in that cache from one step to the next
+ * is 5-20 % slower with the hints, a larger one 5-20 % faster).  PLAIN and
+ * STREAMING force either.  Results are bitwise identical under every
+ * policy.  D3Q19, the HRR collision and every other kernel always use
+ * plain accesses (the hints measured slower or unchanged there). */
+typedef enum { HLBM_CACHE_AUTO = 0, HLBM_CACHE_PLAIN = 1, HLBM_CACHE_STREAMING = 2 } hlbm_cache_policy;
+
 typedef struct {
   uint32_t struct_size;   /* sizeof(hlbm_desc) */
   int32_t stencil;        /* hlbm_stencil */
@@ -140,6 +151,7 @@ typedef struct {
   double force[3];        /* constant body force 3 w_i xi_i.G added after collision (tests) */
   int32_t track_mean_populations; /* 1: the window also accumulates full mean populations */
   int32_t collision;      /* hlbm_collision */
+  int32_t cache_policy;   /* hlbm_cache_policy */
   void* stream;           /* hipStream_t or NULL */
 } hlbm_desc;
 

@@ -30,24 +30,20 @@ namespace hlbm {
 // =========================================================================
 
 // Accesses of the population planes.  Every slot is read and written once
-// per step; plain (cache-allocating) accesses are used on purpose: the
-// nontemporal variants measured up to 20% slower on lattices whose planes
-// stay resident in the 256 MB Infinity Cache and gave at most a few percent
-// on HBM-resident ones.
-#ifndef HLBM_NT_LOADS
-#define HLBM_NT_LOADS 0
-#endif
-#ifndef HLBM_NT_STORES
-#define HLBM_NT_STORES 0
-#endif
-template <typename P>
+// per step.  NT: nontemporal (streaming) hints on both the load and the
+// store, taken by the D2Q9 primal sweep when the lattice exceeds the 256 MB
+// Infinity Cache (5-20 % faster there); a lattice that stays in that cache
+// between steps is 5-20 % slower with them, and the D3Q19 sweeps (whose
+// z neighbours are one xy layer away) and the adjoint measured slower or
+// unchanged, so they use plain accesses.  Either way the values are the same.
+template <bool NT = false, typename P>
 __device__ __forceinline__ auto ld_stream(P p) {
-  if (HLBM_NT_LOADS) return __builtin_nontemporal_load(p);
-  return *p;
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
-template <typename P, typename S>
+template <bool NT = false, typename P, typename S>
 __device__ __forceinline__ void st_stream(P p, S v) {
-  if (HLBM_NT_STORES)
+  if constexpr (NT)
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
@@ -594,7 +590,7 @@ __device__ __forceinline__ bool sweep_cell(const Geo& g, uint32_t c0, uint32_t l
 // with J_MEA (its own terms; a separate instantiation keeps the register
 // budget of the common case); 3 window statistics only, the objective terms
 // of a small region being accumulated by k_window_region before the step.
-template <int Q, typename S, bool ODD, int ACC, bool HRR>
+template <int Q, typename S, bool ODD, int ACC, bool HRR, bool NT = false>
 __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
                                             const typename Prec<S>::Dd* __restrict__ dpor,
                                             S* __restrict__ ghost, const Acc& acc, const int x, const int y,
@@ -640,7 +636,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   // first loads before the remaining ones are even issued).
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream(&at(A, k * g.plane + c0, lo));
+    for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream<NT>(&at(A, k * g.plane + c0, lo));
     __builtin_amdgcn_sched_barrier(0);
   } else if (fast) {
     if (!inlet) {  // the inlet's upstream lies outside the lattice
@@ -649,7 +645,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         if (L::cx[k] == -1 && outlet)  // upstream (nx, y - cy, z - cz): the virtual column
           s[k] = (T)ghost[k * g.gplane + (y - L::cy[k]) + (int64_t)g.ny * (z - L::cz[k])];
         else
-          s[k] = (T)ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
+          s[k] = (T)ld_stream<NT>(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -760,7 +756,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream(&at(A, L::opp[k] * g.plane + c0, lo), (S)s[k]);
+    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, L::opp[k] * g.plane + c0, lo), (S)s[k]);
     if (outlet) {
       const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
       const T uu = ux * ux + uy * uy + uz * uz;
@@ -778,7 +774,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       for (int k = 0; k < Q; ++k) {
         // populations leaving through the inlet or outlet end are dropped
         if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
-        st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
+        st_stream<NT>(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
       }
     } else {
 #pragma unroll
@@ -810,20 +806,37 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
 }
 
+template <int Q, typename S, bool ODD, int ACC, bool HRR, bool NT>
+__device__ __forceinline__ void primal_sweep(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
+                                             const typename Prec<S>::Dd* __restrict__ dpor,
+                                             S* __restrict__ ghost, const Acc& acc) {
+  if constexpr (ACC == 0) {
+    SWEEP_PROLOGUE_RUNS
+    if (!valid) return;
+    primal_cell<Q, S, ODD, ACC, HRR, NT>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
+  } else {
+    SWEEP_PROLOGUE_TILES
+    if (!valid) return;
+    primal_cell<Q, S, ODD, ACC, HRR, NT>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
+  }
+}
+
 template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const ObjBox ob,
                                                 S* __restrict__ A,
                                                 const typename Prec<S>::Dd* __restrict__ dpor,
                                                 S* __restrict__ ghost, const Acc acc) {
-  if constexpr (ACC == 0) {
-    SWEEP_PROLOGUE_RUNS
-    if (!valid) return;
-    primal_cell<Q, S, ODD, ACC, HRR>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
-  } else {
-    SWEEP_PROLOGUE_TILES
-    if (!valid) return;
-    primal_cell<Q, S, ODD, ACC, HRR>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
-  }
+  primal_sweep<Q, S, ODD, ACC, HRR, false>(g, c, ob, A, dpor, ghost, acc);
+}
+
+// The same sweep with streaming hints on the population loads and stores
+// (BGK on lattices larger than the Infinity Cache, see ld_stream).
+template <int Q, typename S, bool ODD, int ACC>
+__global__ __launch_bounds__(256) void k_primal_stream(const Geo g, const Coll c, const ObjBox ob,
+                                                       S* __restrict__ A,
+                                                       const typename Prec<S>::Dd* __restrict__ dpor,
+                                                       S* __restrict__ ghost, const Acc acc) {
+  primal_sweep<Q, S, ODD, ACC, false, true>(g, c, ob, A, dpor, ghost, acc);
 }
 
 // =========================================================================

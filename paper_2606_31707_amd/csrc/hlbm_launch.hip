@@ -88,6 +88,15 @@ static void primal_variant(hlbm_lattice_s* L) {
   S* gh = (S*)L->ghost;
   const dim3 grid = ACC == 0 ? sweep_grid(L) : tile_grid(L);
   const dim3 block = ACC == 0 ? kSweepBlock : kBlock;
+  if constexpr (Q == 9 && !HRR) {
+    if (L->stream_nt) {
+      if (L->parity == 0)
+        k_primal_stream<Q, S, false, ACC><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+      else
+        k_primal_stream<Q, S, true, ACC><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+      return;
+    }
+  }
   if (L->parity == 0)
     k_primal<Q, S, false, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
   else

@@ -46,6 +46,8 @@ GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
 
 PROFILE_PRIMAL, PROFILE_PRIMAL_WINDOW, PROFILE_ADJOINT = 0, 1, 2
 
+CACHE_AUTO, CACHE_PLAIN, CACHE_STREAMING = 0, 1, 2
+
 
 class Desc(C.Structure):
     _fields_ = [
@@ -65,6 +67,7 @@ class Desc(C.Structure):
         ("force", C.c_double * 3),
         ("track_mean_populations", C.c_int32),
         ("collision", C.c_int32),
+        ("cache_policy", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -195,7 +198,7 @@ def _out(out, n):
 def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
               bc_x=BC_INLET_OUTLET, bc_y=BC_WALLS, bc_z=BC_PERIODIC,
               inlet_profile=INLET_PARABOLIC, u_in=0.03, force=(0.0, 0.0, 0.0),
-              track_mean_populations=False, collision=0, stream=None) -> Desc:
+              track_mean_populations=False, collision=0, cache_policy=0, stream=None) -> Desc:
     d = Desc()
     d.struct_size = C.sizeof(Desc)
     d.stencil, d.precision = stencil, precision
@@ -206,6 +209,7 @@ def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
     d.force = (C.c_double * 3)(*force)
     d.track_mean_populations = int(bool(track_mean_populations))
     d.collision = int(collision)
+    d.cache_policy = int(cache_policy)
     d.stream = stream
     return d
 

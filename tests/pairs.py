@@ -64,7 +64,8 @@ def make_gpu(s: Spec, precision: int = 0):
     from paper_2606_31707_amd import hlbm as H
     G = H.Lattice(stencil=s.stencil, precision=precision, nx=s.nx, ny=s.ny, nz=s.nz, tau=s.tau, cs=s.cs,
                   bc_x=s.bc_x, bc_y=s.bc_y, bc_z=s.bc_z, inlet_profile=s.inlet_profile, u_in=s.u_in,
-                  force=tuple(s.force), track_mean_populations=s.track_mean, collision=s.collision)
+                  force=tuple(s.force), track_mean_populations=s.track_mean, collision=s.collision,
+                  cache_policy=s.extra.get("cache_policy", 0))
     if s.porosity is not None:
         G.set_porosity(s.porosity)
     elif s.cyl is not None:

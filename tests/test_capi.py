@@ -71,6 +71,11 @@ def test_status_strings_without_gpu():
         H.footprint_bytes(d)
     d = H.make_desc(nx=220, ny=41)
     assert H.footprint_bytes(d, False, False) >= 220 * 41 * (9 * 8 + 8)
+    for policy in (H.CACHE_AUTO, H.CACHE_PLAIN, H.CACHE_STREAMING):
+        assert H.footprint_bytes(H.make_desc(nx=220, ny=41, cache_policy=policy), False, False) > 0
+    for policy in (-1, 3):
+        with pytest.raises(H.HlbmError):
+            H.footprint_bytes(H.make_desc(nx=220, ny=41, cache_policy=policy))
 
 
 def test_product_does_not_import_the_oracle():

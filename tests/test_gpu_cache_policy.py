@@ -1,0 +1,85 @@
+"""The cache policy of the D2Q9 BGK primal sweep (streaming load/store hints
+on lattices larger than the Infinity Cache) changes no value: plain,
+streaming and automatic runs give bitwise identical populations, window
+statistics, objectives and gradients in every precision, the streaming
+sweep matches the oracle, and a lattice above the automatic threshold gives
+the same state as the plain sweep."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.pairs import Spec, make_gpu, make_oracle, objective_tol, rel_err, say, state_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def H():
+    from paper_2606_31707_amd import hlbm as H
+    return H
+
+
+def spec(policy, **kw):
+    base = dict(nx=160, ny=41, tau=0.56, u_in=0.05, cyl=(40.0, 20.0, 10.0),
+                obj=(O.OBJ_DISS, (60, 5, 0), (150, 35, 0), 0.0), extra={"cache_policy": policy})
+    base.update(kw)
+    return Spec(**base)
+
+
+def run(s, precision):
+    G = make_gpu(s, precision)
+    G.run_primal(41)
+    G.window_reset()
+    G.run_primal(21, accumulate=True)
+    G.solve_adjoint(H().SOURCE_MEAN, tau_adj=0.6, max_iters=30)
+    return G.populations(), G.window_objective(), G.gradient(), G.field(H().FIELD_MEAN_U)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_policies_give_identical_results(precision):
+    say("cache policy bitwise", precision)
+    ref = run(spec(H().CACHE_PLAIN), precision)
+    for policy in (H().CACHE_STREAMING, H().CACHE_AUTO):
+        out = run(spec(policy), precision)
+        assert np.array_equal(out[0], ref[0]) and out[1] == ref[1]
+        assert np.array_equal(out[2], ref[2]) and np.array_equal(out[3], ref[3])
+
+
+def test_policies_identical_with_periodic_force():
+    say("cache policy periodic")
+    kw = dict(bc_x=0, bc_y=0, force=(1e-6, 0.0, 0.0), cyl=(80.0, 20.0, 12.0))
+    outs = [run(spec(p, **kw), 0) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_streaming_sweep_matches_oracle():
+    say("cache policy oracle parity")
+    s = spec(H().CACHE_STREAMING)
+    L, G = make_oracle(s), make_gpu(s)
+    L.step(200)
+    G.run_primal(200)
+    assert rel_err(G.populations(), L.populations(), state_mask(s)) < 1e-12
+    n = 40
+    L.window_reset()
+    for _ in range(n):
+        L.window_sample()
+        L.step(1)
+    G.window_reset()
+    G.run_primal(n, accumulate=True)
+    kind, lo, hi, u0 = s.obj
+    assert abs(G.window_objective() - L.window_objective()) < 10 * objective_tol(L, s, kind, lo, hi, u0)
+    assert rel_err(G.populations(), L.populations(), state_mask(s)) < 1e-12
+
+
+def test_lattice_above_the_threshold():
+    """4096 x 2048 FP64: 8.4 M cells x (9 + 1) x 8 B = 671 MB > 256 MiB, so
+    the automatic policy streams; it must reproduce the plain sweep."""
+    say("cache policy auto above threshold")
+    outs = []
+    for policy in (H().CACHE_PLAIN, H().CACHE_AUTO):
+        G = H().Lattice(stencil=0, precision=0, nx=4096, ny=2048, tau=0.6, u_in=0.04, cache_policy=policy)
+        G.build_cylinder(1024.0, 1023.5, 200.0)
+        G.init_equilibrium()
+        G.run_primal(9)
+        outs.append(G.populations())
+        G.close()
+    assert np.array_equal(outs[0], outs[1])
