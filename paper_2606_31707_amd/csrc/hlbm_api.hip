@@ -335,12 +335,12 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
     return fail(HLBM_E_INVALID, "internal: plane stride %lld < %lld cells", pl, nn);
   }
   L->stream = (hipStream_t)desc->stream;
-  // streaming hints for D2Q9 BGK primal sweeps over lattices larger than the
-  // 256 MiB Infinity Cache (measured: 160 MB slower with them, 320 MB faster)
+  // streaming hints for BGK primal sweeps over lattices larger than the
+  // 256 MiB Infinity Cache (D2Q9 measured 160 MB slower with them, 320 MB
+  // faster); which steps take them is decided per stencil at launch
   const int64_t sweep_bytes = (int64_t)(L->ssize * L->q + L->dsize) * L->plane;
-  L->stream_nt = desc->stencil == HLBM_D2Q9 &&
-                 (desc->cache_policy == HLBM_CACHE_STREAMING ||
-                  (desc->cache_policy == HLBM_CACHE_AUTO && sweep_bytes > ((int64_t)256 << 20)));
+  L->stream_nt = desc->cache_policy == HLBM_CACHE_STREAMING ||
+                 (desc->cache_policy == HLBM_CACHE_AUTO && sweep_bytes > ((int64_t)256 << 20));
   auto bail = [&](hlbm_status st) {
     hlbm_destroy(L);
     return st;

@@ -31,11 +31,12 @@ namespace hlbm {
 
 // Accesses of the population planes.  Every slot is read and written once
 // per step.  NT: nontemporal (streaming) hints on both the load and the
-// store, taken by the D2Q9 primal sweep when the lattice exceeds the 256 MB
-// Infinity Cache (5-20 % faster there); a lattice that stays in that cache
-// between steps is 5-20 % slower with them, and the D3Q19 sweeps (whose
-// z neighbours are one xy layer away) and the adjoint measured slower or
-// unchanged, so they use plain accesses.  Either way the values are the same.
+// store, taken by the BGK primal sweep when the lattice exceeds the 256 MB
+// Infinity Cache: both D2Q9 steps (5-20 % faster there) and the D3Q19 even
+// step (1-2 %; its odd step, whose z neighbours reuse lines one xy layer
+// later, is 7 % slower with them).  A lattice that stays in that cache
+// between steps is 5-20 % slower with them, and the adjoint measured slower
+// or unchanged, so it uses plain accesses.  Either way the values are the same.
 template <bool NT = false, typename P>
 __device__ __forceinline__ auto ld_stream(P p) {
   if constexpr (NT) return __builtin_nontemporal_load(p);

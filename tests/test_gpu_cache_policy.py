@@ -1,9 +1,9 @@
-"""The cache policy of the D2Q9 BGK primal sweep (streaming load/store hints
-on lattices larger than the Infinity Cache) changes no value: plain,
-streaming and automatic runs give bitwise identical populations, window
-statistics, objectives and gradients in every precision, the streaming
-sweep matches the oracle, and a lattice above the automatic threshold gives
-the same state as the plain sweep."""
+"""The cache policy of the BGK primal sweep (streaming load/store hints on
+lattices larger than the Infinity Cache) changes no value: plain, streaming
+and automatic runs give bitwise identical populations, window statistics,
+objectives and gradients in every precision, for D2Q9 and D3Q19 with the
+Smagorinsky closure, the streaming sweep matches the oracle, and a lattice
+above the automatic threshold gives the same state as the plain sweep."""
 import numpy as np
 import pytest
 
@@ -49,6 +49,16 @@ def test_policies_identical_with_periodic_force():
     kw = dict(bc_x=0, bc_y=0, force=(1e-6, 0.0, 0.0), cyl=(80.0, 20.0, 12.0))
     outs = [run(spec(p, **kw), 0) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_policies_identical_d3q19_les(precision):
+    say("cache policy d3q19", precision)
+    kw = dict(stencil=1, nx=40, ny=24, nz=16, tau=0.52, cs=0.12, bc_z=0, cyl=(12.0, 11.5, 6.0), track_mean=True,
+              obj=(O.OBJ_DISS, (16, 2, 0), (36, 21, 15), 0.0))
+    outs = [run(spec(p, **kw), precision) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][3], outs[1][3])
 
 
 def test_streaming_sweep_matches_oracle():
