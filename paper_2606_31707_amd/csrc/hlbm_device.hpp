@@ -209,12 +209,20 @@ __device__ __forceinline__ double block_max256(double v, double* lds) {
 // round-robin over the XCDs, each with its own L2; renumbering them so that
 // XCD k takes one contiguous range of tiles (row-major) keeps x-neighbouring
 // tiles, whose odd-step pulls and pushes share the cache lines at the tile
-// edges, in the same L2.  b -> tile is a bijection of [0, nt).
+// edges, in the same L2.  When the whole grid is resident at once (at most
+// 2048 workgroups: 256 CUs x 8 workgroups of 256 threads), the dispatch order
+// decides which tiles finish last; there the last XCD walks its range from
+// the end, so that the tiles of the last rows (a wall row takes the longer
+// boundary path) start first rather than last (2 % per step on the
+// 1100 x 410 channel; on larger grids the reversed walk measured 2-4 %
+// slower).  b -> tile is a bijection of [0, nt): the last XCD's range has q
+// tiles (r < NXCD) and k < q there.
 __device__ __forceinline__ int sweep_tile(int b, int nt) {
   if (!HLBM_XCD_REMAP) return b;
   const int q = nt / NXCD, r = nt % NXCD;
   const int xcd = b % NXCD, k = b / NXCD;
-  return xcd * q + (xcd < r ? xcd : r) + k;
+  const int start = xcd * q + (xcd < r ? xcd : r);
+  return (xcd == NXCD - 1 && nt <= 2048) ? start + (q - 1 - k) : start + k;
 }
 
 __device__ __forceinline__ int linear_block() {
