@@ -804,8 +804,11 @@ def main():
     q.G.synchronize()
     t0 = time.perf_counter()
     lu = 0
+    each = []  # wall time of every timed query (each ends on its host-side results)
     for i in range(args.steps):
+        tq = time.perf_counter()
         lu += q.run()
+        each.append(time.perf_counter() - tq)
         log(f"step {i}: period {q.period}, window {q.window}, J {q.J:.6e}, adjoint {q.adj_iters} it, "
             f"residual {q.adj_res:.2e}")
     q.G.synchronize()
@@ -834,6 +837,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded porosity noise on the cylinder rim)",
+        "query_latency_s": {"p50": float(np.median(each)), "max": float(np.max(each)),
+                            "each": [round(v, 4) for v in each],
+                            "note": "one query at a time; latency under a Poisson query stream: --report serving"},
         "config": {"workload": w.name, "cells": n, "primal_steps": T, "window_steps": q.window,
                    "shedding_period_steps": q.period, "objective": "dissipation",
                    "adjoint": f"mean-flow, tol {args.adjoint_tol:g}", "adjoint_iters": q.adj_iters,
