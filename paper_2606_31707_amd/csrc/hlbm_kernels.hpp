@@ -787,11 +787,15 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (L::cx[k] != -1) continue;
-        int vx = x, vy = y + L::cy[k], vz = z + L::cz[k];
-        if (classify(g, vx, vy, vz) != NB_CELL) continue;
         const T cu = (T)L::cx[k] * ux + (T)L::cy[k] * uy + (T)L::cz[k] * uz;
         const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
-        A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
+        if (fast) {  // away from walls and seams (nx-1, y+cy, z+cz) is a lattice cell
+          at(A, k * g.plane + c0 + (int64_t)L::cy[k] * g.nx + (int64_t)L::cz[k] * g.nx * g.ny, lo) = (S)vs;
+        } else {
+          int vx = x, vy = y + L::cy[k], vz = z + L::cz[k];
+          if (classify(g, vx, vy, vz) != NB_CELL) continue;
+          A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
+        }
       }
     }
   }
