@@ -246,18 +246,19 @@ def traffic_for(kernel_hash: str):
     return rec.get("bytes_per_launch")
 
 
+# The profiling commands, with {out} the directory given to --profile-summary.
 PROFILE_CMDS = {
-    "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv -- "
+    "trace": "rocprofv3 --kernel-trace --stats -d {out}/trace -o bench --output-format csv -- "
              "python3 bench.py",
-    "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/FETCH_SIZE -o bench --output-format csv -- "
+    "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d {out}/FETCH_SIZE -o bench --output-format csv -- "
                   "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 400 "
                   "--adjoint-max 100 --profile-every 0",
-    "WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/WRITE_SIZE -o bench --output-format csv -- "
+    "WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d {out}/WRITE_SIZE -o bench --output-format csv -- "
                   "python3 bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu-baseline --primal-steps 400 "
                   "--adjoint-max 100 --profile-every 0",
-    "copy_FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copy_FETCH_SIZE -o copy --output-format csv "
+    "copy_FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE -d {out}/copy_FETCH_SIZE -o copy --output-format csv "
                        "-- python3 bench.py --copy-calibration-mib 512",
-    "copy_WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copy_WRITE_SIZE -o copy --output-format csv "
+    "copy_WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE -d {out}/copy_WRITE_SIZE -o copy --output-format csv "
                        "-- python3 bench.py --copy-calibration-mib 512",
 }
 PRIMAL_EVEN = "hlbm::k_primal<9, double, false, 0, false>"
@@ -284,7 +285,7 @@ def summarize_profiles(d: str):
     mean_us = 0.5 * (us[PRIMAL_EVEN] + us[PRIMAL_ODD])
     lines = ["# Kernel trace: vortex_re100 (1100x410, D2Q9, FP64) gradient query", "",
              "Command (run from the repository root on the MI355X box, `export TMPDIR=/tmp`):", "", "```",
-             PROFILE_CMDS["trace"], "```", "",
+             PROFILE_CMDS["trace"].format(out=d), "```", "",
              "The benchmark command itself (warm-up query, three timed FP64 queries, the FP32 query and the "
              "CPU-oracle sample); the FP32 kernels appear under their own names.", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
@@ -333,7 +334,8 @@ def summarize_profiles(d: str):
         "bytes_per_launch": rd + wr, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
         "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (rd + wr) / alg,
         "kernel_source_sha256": kernel_source_hash(),
-        "commands": [PROFILE_CMDS[k] for k in ("FETCH_SIZE", "WRITE_SIZE", "copy_FETCH_SIZE", "copy_WRITE_SIZE")],
+        "commands": [PROFILE_CMDS[k].format(out=d)
+                     for k in ("FETCH_SIZE", "WRITE_SIZE", "copy_FETCH_SIZE", "copy_WRITE_SIZE")],
     }
     lines += ["", "Counter traffic per launch of the same kernel (rocprofv3 `--pmc FETCH_SIZE`, then "
                   "`--pmc WRITE_SIZE`, each scaled by the value the counter reads for a plain 512 MiB device "
@@ -787,8 +789,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is in "
-              "DESIGN.md); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run it with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     w = I.vortex_re100()
