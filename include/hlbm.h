@@ -127,16 +127,17 @@ typedef enum {
  * closure (smagorinsky_cs > 0). */
 typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
 
-/* Cache hints of the population loads and stores of the BGK primal sweep
- * (with or without the window statistics): both AA steps of D2Q9, the even
- * step of D3Q19 (its odd step reuses the lines of the neighbouring xy layer).
+/* Cache hints of the population loads and stores of the BGK sweeps: both AA
+ * steps of the D2Q9 primal sweep (with or without the window statistics),
+ * the even step of the D3Q19 primal sweep (its odd step reuses the lines of
+ * the neighbouring xy layer) and the even step of the adjoint sweep.
  * AUTO: streaming (nontemporal) hints when the populations and the porosity
  * exceed 256 MiB, the size of the MI355X Infinity Cache, plain accesses
  * otherwise (a lattice that stays in that cache from one step to the next
- * is 5-20 % slower with the hints, a larger D2Q9 one 5-20 % faster, D3Q19
- * 1-2 %).  PLAIN and STREAMING force either.  Results are bitwise identical
- * under every policy.  The HRR collision and every other kernel always use
- * plain accesses (the hints measured slower or unchanged there). */
+ * is 5-20 % slower with the hints, a larger D2Q9 one 5-20 % faster (adjoint
+ * 4-5 %), D3Q19 1-2 %).  PLAIN and STREAMING force either.  Results are
+ * bitwise identical under every policy.  The HRR collision and every other
+ * kernel always use plain accesses. */
 typedef enum { HLBM_CACHE_AUTO = 0, HLBM_CACHE_PLAIN = 1, HLBM_CACHE_STREAMING = 2 } hlbm_cache_policy;
 
 typedef struct {

@@ -31,12 +31,13 @@ namespace hlbm {
 
 // Accesses of the population planes.  Every slot is read and written once
 // per step.  NT: nontemporal (streaming) hints on both the load and the
-// store, taken by the BGK primal sweep when the lattice exceeds the 256 MB
-// Infinity Cache: both D2Q9 steps (5-20 % faster there) and the D3Q19 even
-// step (1-2 %; its odd step, whose z neighbours reuse lines one xy layer
-// later, is 7 % slower with them).  A lattice that stays in that cache
-// between steps is 5-20 % slower with them, and the adjoint measured slower
-// or unchanged, so it uses plain accesses.  Either way the values are the same.
+// store, taken by the BGK sweeps when the lattice exceeds the 256 MB
+// Infinity Cache: both D2Q9 primal steps (5-20 % faster there), the D3Q19
+// primal even step (1-2 %; its odd step, whose z neighbours reuse lines one
+// xy layer later, is 7 % slower with them) and the adjoint's even step
+// (D2Q9 4-5 %, D3Q19 1 %; both adjoint steps together measured up to 9 %
+// slower).  A lattice that stays in that cache between steps is 5-20 %
+// slower with them.  Either way the values are the same.
 template <bool NT = false, typename P>
 __device__ __forceinline__ auto ld_stream(P p) {
   if constexpr (NT) return __builtin_nontemporal_load(p);
@@ -1836,7 +1837,7 @@ __device__ __forceinline__ double hrr_dphi_dd(const double (&ph)[Q], const doubl
   return dA + (1.0 - omega) * dB;
 }
 
-template <int Q, typename SA, bool ODD, bool HRR, bool MEA>
+template <int Q, typename SA, bool ODD, bool HRR, bool MEA, bool NT = false>
 __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, const AdjC& ac, SA* __restrict__ A,
                                              const SA* __restrict__ prep, const double* __restrict__ src,
                                              const double* __restrict__ oprep, const SA* __restrict__ pv_in,
@@ -1879,7 +1880,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   T ph[Q];  // phihat_k = phi_opp(k)
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) ph[k] = ld_stream(&at(A, k * g.plane + c0, lo));
+    for (int k = 0; k < Q; ++k) ph[k] = ld_stream<NT>(&at(A, k * g.plane + c0, lo));
     __builtin_amdgcn_sched_barrier(0);
     if (outlet) adjoint_zero_outlet<Q, SA>(g, x, y, z, ph);
   } else if (fast) {
@@ -2040,7 +2041,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
 
   if (!ODD) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_stream(&at(A, i * g.plane + c0, lo), lam[i]);
+    for (int i = 0; i < Q; ++i) st_stream<NT>(&at(A, i * g.plane + c0, lo), lam[i]);
   } else if (fast) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -2072,6 +2073,21 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
   SWEEP_PROLOGUE_TILES
   if (!valid) return;
   adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
+}
+
+// The even adjoint step with streaming hints on the phi accesses (BGK on
+// lattices larger than the Infinity Cache, see ld_stream; 4-5 % faster there
+// for D2Q9, 1 % for D3Q19, 9 % slower on a cache-resident lattice).
+template <int Q, typename SA, bool MEA>
+__global__ __launch_bounds__(256) void k_adjoint_stream(const Geo g, const ObjBox ob, const AdjC ac,
+                                                        SA* __restrict__ A, const SA* __restrict__ prep,
+                                                        const double* __restrict__ src,
+                                                        const double* __restrict__ oprep,
+                                                        const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
+  SWEEP_PROLOGUE_TILES
+  if (!valid) return;
+  adjoint_cell<Q, SA, false, false, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
+                                               tile_lo);
 }
 
 struct PackedAdjoint {

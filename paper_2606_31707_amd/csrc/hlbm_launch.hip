@@ -397,6 +397,11 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L) {
     } else {
       if (odd) HLBM_ADJ(true, true, false); else HLBM_ADJ(false, true, false);
     }
+  } else if (!odd && L->stream_nt) {  // streaming hints: even step, lattices above the Infinity Cache
+    if (mea)
+      k_adjoint_stream<Q, SA, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout);
+    else
+      k_adjoint_stream<Q, SA, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout);
   } else {
     if (mea) {
       if (odd) HLBM_ADJ(true, false, true); else HLBM_ADJ(false, false, true);
