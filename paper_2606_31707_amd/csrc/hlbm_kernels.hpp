@@ -626,12 +626,13 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   const T d = (T)at(dpor, c0, lo);
   // Window sums of rho and j: their old values are requested with the
   // populations (and all of them before any is written back, see
-  // accumulate_terms).  The inlet's slots are read but not updated.
+  // accumulate_terms).  The inlet's slots are read but not updated.  The
+  // dense window sums take the populations' cache hints.
   double wold[L::D + 1];
   if constexpr (ACC != 0) {
-    wold[0] = at(acc.rho, c0, lo);
+    wold[0] = ld_stream<NT>(&at(acc.rho, c0, lo));
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) wold[1 + a] = at(acc.j, a * g.plane + c0, lo);
+    for (int a = 0; a < L::D; ++a) wold[1 + a] = ld_stream<NT>(&at(acc.j, a * g.plane + c0, lo));
   }
   // All population loads are issued before any arithmetic on them (the
   // scheduler otherwise interleaves early sums, which forces a wait for the
@@ -689,23 +690,26 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   (void)oay;
   (void)oaz;
   if (ACC != 0 && !inlet) {  // the pinned inlet is not part of the window
-    at(acc.rho, c0, lo) = wold[0] + (double)drho;
-    at(acc.j, c0, lo) = wold[1] + (double)jx;
-    at(acc.j, g.plane + c0, lo) = wold[2] + (double)jy;
-    if constexpr (L::D == 3) at(acc.j, 2 * g.plane + c0, lo) = wold[3] + (double)jz;
+    st_stream<NT>(&at(acc.rho, c0, lo), wold[0] + (double)drho);
+    st_stream<NT>(&at(acc.j, c0, lo), wold[1] + (double)jx);
+    st_stream<NT>(&at(acc.j, g.plane + c0, lo), wold[2] + (double)jy);
+    if constexpr (L::D == 3) st_stream<NT>(&at(acc.j, 2 * g.plane + c0, lo), wold[3] + (double)jz);
     if (acc.f) {  // in groups of 4 (read, then write back)
 #pragma unroll
       for (int k0 = 0; k0 < Q; k0 += 4) {
         double o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (k0 + i < Q) o[i] = at(acc.f, (k0 + i) * g.plane + c0, lo);
+          if (k0 + i < Q) o[i] = ld_stream<NT>(&at(acc.f, (k0 + i) * g.plane + c0, lo));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (k0 + i < Q) at(acc.f, (k0 + i) * g.plane + c0, lo) = o[i] + (double)s[k0 + i];
+          if (k0 + i < Q) st_stream<NT>(&at(acc.f, (k0 + i) * g.plane + c0, lo), o[i] + (double)s[k0 + i]);
       }
     }
-    if (acc.tau) at(acc.tau, c0, lo) += (double)taue;
+    if (acc.tau) {
+      const double ot = ld_stream<NT>(&at(acc.tau, c0, lo));
+      st_stream<NT>(&at(acc.tau, c0, lo), ot + (double)taue);
+    }
     if constexpr (ACC == 1 || ACC == 2) in_region = region_index<Q>(ob, x, y, z, r);
     if (in_region) {
       double sd[Q];
