@@ -4,6 +4,8 @@ and automatic runs give bitwise identical populations, window statistics,
 objectives and gradients in every precision, for D2Q9 and D3Q19 with the
 Smagorinsky closure, the streaming sweep matches the oracle, and a lattice
 above the automatic threshold gives the same state as the plain sweep."""
+import math
+
 import numpy as np
 import pytest
 
@@ -42,6 +44,18 @@ def test_policies_give_identical_results(precision):
         out = run(spec(policy), precision)
         assert np.array_equal(out[0], ref[0]) and out[1] == ref[1]
         assert np.array_equal(out[2], ref[2]) and np.array_equal(out[3], ref[3])
+
+
+@pytest.mark.parametrize("objective", ["ffa_plane", "mea_box"])
+def test_policies_identical_region_pass_and_mea(objective):
+    """The small-region window (objective terms by a separate pass) and J_MEA
+    (its own window and adjoint kernels) under both policies."""
+    say("cache policy", objective)
+    obj = {"ffa_plane": (O.OBJ_FFA, (90, 0, 0), (90, 40, 0), 0.05),
+           "mea_box": (O.OBJ_MEA, (30, 8, 0), (50, 32, 0), math.pi * 10.0)}[objective]
+    outs = [run(spec(p, obj=obj), 0) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][3], outs[1][3])
 
 
 def test_policies_identical_with_periodic_force():
