@@ -136,8 +136,8 @@ typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
  * otherwise (a lattice that stays in that cache from one step to the next
  * is 5-20 % slower with the hints, a larger D2Q9 one 5-20 % faster (adjoint
  * 4-5 %), D3Q19 1-2 %).  PLAIN and STREAMING force either.  Results are
- * bitwise identical under every policy.  The HRR collision and every other
- * kernel always use plain accesses. */
+ * bitwise identical under every policy, for either collision.  Every other
+ * kernel uses plain accesses. */
 typedef enum { HLBM_CACHE_AUTO = 0, HLBM_CACHE_PLAIN = 1, HLBM_CACHE_STREAMING = 2 } hlbm_cache_policy;
 
 typedef struct {

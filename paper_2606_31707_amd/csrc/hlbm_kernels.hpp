@@ -840,13 +840,13 @@ __global__ __launch_bounds__(256) void k_primal(const Geo g, const Coll c, const
 }
 
 // The same sweep with streaming hints on the population loads and stores
-// (BGK on lattices larger than the Infinity Cache, see ld_stream).
-template <int Q, typename S, bool ODD, int ACC>
+// (lattices larger than the Infinity Cache, see ld_stream).
+template <int Q, typename S, bool ODD, int ACC, bool HRR>
 __global__ __launch_bounds__(256) void k_primal_stream(const Geo g, const Coll c, const ObjBox ob,
                                                        S* __restrict__ A,
                                                        const typename Prec<S>::Dd* __restrict__ dpor,
                                                        S* __restrict__ ghost, const Acc acc) {
-  primal_sweep<Q, S, ODD, ACC, false, true>(g, c, ob, A, dpor, ghost, acc);
+  primal_sweep<Q, S, ODD, ACC, HRR, true>(g, c, ob, A, dpor, ghost, acc);
 }
 
 // =========================================================================
@@ -2079,10 +2079,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
   adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
 }
 
-// The even adjoint step with streaming hints on the phi accesses (BGK on
-// lattices larger than the Infinity Cache, see ld_stream; 4-5 % faster there
-// for D2Q9, 1 % for D3Q19, 9 % slower on a cache-resident lattice).
-template <int Q, typename SA, bool MEA>
+// The even adjoint step with streaming hints on the phi accesses (lattices
+// larger than the Infinity Cache, see ld_stream; 4-5 % faster there for
+// D2Q9, 1 % for D3Q19, 9 % slower on a cache-resident lattice).
+template <int Q, typename SA, bool HRR, bool MEA>
 __global__ __launch_bounds__(256) void k_adjoint_stream(const Geo g, const ObjBox ob, const AdjC ac,
                                                         SA* __restrict__ A, const SA* __restrict__ prep,
                                                         const double* __restrict__ src,
@@ -2090,8 +2090,8 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(const Geo g, const ObjBo
                                                         const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
   SWEEP_PROLOGUE_TILES
   if (!valid) return;
-  adjoint_cell<Q, SA, false, false, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
-                                               tile_lo);
+  adjoint_cell<Q, SA, false, HRR, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
+                                             tile_lo);
 }
 
 struct PackedAdjoint {

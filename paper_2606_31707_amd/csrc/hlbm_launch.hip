@@ -92,16 +92,14 @@ static void primal_variant(hlbm_lattice_s* L) {
   // only the D3Q19 even step, whose accesses are the cell's own slots (the
   // odd step's z neighbours reuse lines one xy layer later and ran 7 %
   // slower with the hints).
-  if constexpr (!HRR) {
-    if (L->stream_nt) {
-      if (L->parity == 0) {
-        k_primal_stream<Q, S, false, ACC><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
-        return;
-      }
-      if constexpr (Q == 9) {
-        k_primal_stream<Q, S, true, ACC><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
-        return;
-      }
+  if (L->stream_nt) {
+    if (L->parity == 0) {
+      k_primal_stream<Q, S, false, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+      return;
+    }
+    if constexpr (Q == 9) {
+      k_primal_stream<Q, S, true, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+      return;
     }
   }
   if (L->parity == 0)
@@ -391,17 +389,28 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L) {
 #define HLBM_ADJ(ODD, HRR, MEA)                                                                        \
   k_adjoint<Q, SA, ODD, HRR, MEA><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, \
                                                                    pout)
-  if (hrr) {
+  if (!odd && L->stream_nt) {  // streaming hints: even step, lattices above the Infinity Cache
+    if (hrr) {
+      if (mea)
+        k_adjoint_stream<Q, SA, true, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
+                                                                             pin, pout);
+      else
+        k_adjoint_stream<Q, SA, true, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
+                                                                              pin, pout);
+    } else {
+      if (mea)
+        k_adjoint_stream<Q, SA, false, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
+                                                                              pin, pout);
+      else
+        k_adjoint_stream<Q, SA, false, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src,
+                                                                               L->oprep, pin, pout);
+    }
+  } else if (hrr) {
     if (mea) {
       if (odd) HLBM_ADJ(true, true, true); else HLBM_ADJ(false, true, true);
     } else {
       if (odd) HLBM_ADJ(true, true, false); else HLBM_ADJ(false, true, false);
     }
-  } else if (!odd && L->stream_nt) {  // streaming hints: even step, lattices above the Infinity Cache
-    if (mea)
-      k_adjoint_stream<Q, SA, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout);
-    else
-      k_adjoint_stream<Q, SA, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout);
   } else {
     if (mea) {
       if (odd) HLBM_ADJ(true, false, true); else HLBM_ADJ(false, false, true);

@@ -2,7 +2,7 @@
 lattices larger than the Infinity Cache) changes no value: plain, streaming
 and automatic runs give bitwise identical populations, window statistics,
 objectives and gradients in every precision, for D2Q9 and D3Q19 with the
-Smagorinsky closure, the streaming sweep matches the oracle, and a lattice
+Smagorinsky closure and the HRR collision, the streaming sweep matches the oracle, and a lattice
 above the automatic threshold gives the same state as the plain sweep."""
 import math
 
@@ -54,6 +54,20 @@ def test_policies_identical_region_pass_and_mea(objective):
     obj = {"ffa_plane": (O.OBJ_FFA, (90, 0, 0), (90, 40, 0), 0.05),
            "mea_box": (O.OBJ_MEA, (30, 8, 0), (50, 32, 0), math.pi * 10.0)}[objective]
     outs = [run(spec(p, obj=obj), 0) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][3], outs[1][3])
+
+
+@pytest.mark.parametrize("stencil", [0, 1])
+def test_policies_identical_hrr(stencil):
+    """The HRRLBM-LES collision and its mean-flow adjoint under both policies."""
+    say("cache policy hrr", stencil)
+    if stencil == 0:
+        kw = dict(collision=1, cs=0.15, tau=0.52, track_mean=True)
+    else:
+        kw = dict(stencil=1, nx=40, ny=24, nz=16, tau=0.52, cs=0.12, bc_z=0, cyl=(12.0, 11.5, 6.0),
+                  track_mean=True, collision=1, obj=(O.OBJ_DISS, (16, 2, 0), (36, 21, 15), 0.0))
+    outs = [run(spec(p, **kw), 1) for p in (H().CACHE_PLAIN, H().CACHE_STREAMING)]
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][3], outs[1][3])
 
