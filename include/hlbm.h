@@ -127,7 +127,7 @@ typedef enum {
  * closure (smagorinsky_cs > 0). */
 typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
 
-/* Cache hints of the population loads and stores of the BGK sweeps: both AA
+/* Cache hints of the population loads and stores of the sweeps: both AA
  * steps of the D2Q9 primal sweep (with or without the window statistics),
  * the even step of the D3Q19 primal sweep (its odd step reuses the lines of
  * the neighbouring xy layer) and the even step of the adjoint sweep.

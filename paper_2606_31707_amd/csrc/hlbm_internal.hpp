@@ -22,7 +22,7 @@ struct hlbm_lattice_s {
   void* f = nullptr;      // q * plane stored populations (AA pattern, in place)
   void* dpor = nullptr;   // plane porosity values
   void* ghost = nullptr;  // q * gplane outlet virtual values (even -> odd step)
-  bool stream_nt = false;  // streaming load/store hints in the BGK sweeps
+  bool stream_nt = false;  // streaming load/store hints in the sweeps
   int parity = 0;         // 0: canonical layout; 1: after an even (local) step
   int64_t steps = 0;
 

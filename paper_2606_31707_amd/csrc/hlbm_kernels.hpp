@@ -31,7 +31,7 @@ namespace hlbm {
 
 // Accesses of the population planes.  Every slot is read and written once
 // per step.  NT: nontemporal (streaming) hints on both the load and the
-// store, taken by the BGK sweeps when the lattice exceeds the 256 MB
+// store, taken by the sweeps when the lattice exceeds the 256 MB
 // Infinity Cache: both D2Q9 primal steps (5-20 % faster there), the D3Q19
 // primal even step (1-2 %; its odd step, whose z neighbours reuse lines one
 // xy layer later, is 7 % slower with them) and the adjoint's even step
