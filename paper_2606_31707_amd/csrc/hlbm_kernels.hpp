@@ -51,6 +51,24 @@ __device__ __forceinline__ void st_stream(P p, S v) {
     *p = v;
 }
 
+// Conversion of an arithmetic value to the storage type S.  FP16 storage of
+// an FP32 result always rounds that FP32 value: the opaque copy keeps the
+// compiler from fusing the last multiply-add into the conversion (a
+// mixed-precision FMA rounds the exact result to FP16 once), which it would
+// do or not depending on the shape of the surrounding code, changing rare
+// values by one FP16 unit from one build of the same arithmetic to the next.
+// FP64 values (initialisation, user input) are converted directly.
+template <typename S, typename T>
+__device__ __forceinline__ S to_store(T v) {
+  if constexpr (sizeof(S) == 2 && sizeof(T) == 4) {
+    float t = (float)v;
+    asm("" : "+v"(t));
+    return (S)t;
+  } else {
+    return (S)v;
+  }
+}
+
 // Values that are the same in every lane of a wavefront (tile indices, tile
 // base cells), moved to scalar registers: the integer divisions of the tile
 // decode run on the vector unit, and without this their results, and all
@@ -619,7 +637,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   if (inlet && !fast) {  // odd step, inlet cell of a wall row: pinned, pushed
     inlet_state<Q, T>(g, y, s);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+    for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, to_store<S>(s[k]));
     return;
   }
   // Porosity and populations are requested together.
@@ -762,7 +780,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 
   if (!ODD) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, L::opp[k] * g.plane + c0, lo), (S)s[k]);
+    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, L::opp[k] * g.plane + c0, lo), to_store<S>(s[k]));
     if (outlet) {
       const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
       const T uu = ux * ux + uy * uy + uz * uz;
@@ -771,7 +789,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         if (L::cx[k] != -1) continue;
         const T cu = (T)L::cx[k] * ux + (T)L::cy[k] * uy + (T)L::cz[k] * uz;
         const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
-        ghost[k * g.gplane + y + (int64_t)g.ny * z] = (S)vs;
+        ghost[k * g.gplane + y + (int64_t)g.ny * z] = to_store<S>(vs);
       }
     }
   } else {
@@ -780,11 +798,11 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       for (int k = 0; k < Q; ++k) {
         // populations leaving through the inlet or outlet end are dropped
         if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
-        st_stream<NT>(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), (S)s[k]);
+        st_stream<NT>(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), to_store<S>(s[k]));
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, (S)s[k]);
+      for (int k = 0; k < Q; ++k) push<Q, S>(g, A, x, y, z, cell, k, to_store<S>(s[k]));
     }
     if (outlet) {
       const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
@@ -795,11 +813,11 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
         const T cu = (T)L::cx[k] * ux + (T)L::cy[k] * uy + (T)L::cz[k] * uz;
         const T vs = (T)L::w[k] * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
         if (fast) {  // away from walls and seams (nx-1, y+cy, z+cz) is a lattice cell
-          at(A, k * g.plane + c0 + (int64_t)L::cy[k] * g.nx + (int64_t)L::cz[k] * g.nx * g.ny, lo) = (S)vs;
+          at(A, k * g.plane + c0 + (int64_t)L::cy[k] * g.nx + (int64_t)L::cz[k] * g.nx * g.ny, lo) = to_store<S>(vs);
         } else {
           int vx = x, vy = y + L::cy[k], vz = z + L::cz[k];
           if (classify(g, vx, vy, vz) != NB_CELL) continue;
-          A[k * g.plane + cell_of(g, vx, vy, vz)] = (S)vs;
+          A[k * g.plane + cell_of(g, vx, vy, vz)] = to_store<S>(vs);
         }
       }
     }
@@ -1242,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_init(const Geo g, S* __restrict__ A,
     }
   }
 #pragma unroll
-  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (S)s[k];
+  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = to_store<S>(s[k]);
 }
 
 template <int Q, typename S>
@@ -1269,7 +1287,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Geo g, S* __restrict__ A,
   CELL_PROLOGUE
   if (!valid) return;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = (S)(in[k * n + cell] - L::w[k]);
+  for (int k = 0; k < Q; ++k) A[k * g.plane + cell] = to_store<S>(in[k * n + cell] - L::w[k]);
 }
 
 template <int Q, typename S>
