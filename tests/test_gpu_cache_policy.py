@@ -108,6 +108,36 @@ def test_streaming_sweep_matches_oracle():
     assert rel_err(G.populations(), L.populations(), state_mask(s)) < 1e-12
 
 
+@pytest.mark.parametrize("case", ["d3q19_fp32", "d2q9_fp16s"])
+def test_above_threshold_full_query(case):
+    """Lattices above the 256 MiB threshold (D3Q19 FP32 256 x 128 x 112:
+    3.7 M cells x 80 B = 294 MB; D2Q9 FP16S 8192 x 2048: 16.8 M cells x 22 B
+    = 369 MB): primal, window and mean-flow adjoint under the automatic policy
+    (streaming kernels) reproduce the plain sweeps bitwise."""
+    say("cache policy above threshold", case)
+    if case == "d3q19_fp32":
+        kw = dict(stencil=1, precision=1, nx=256, ny=128, nz=112, tau=0.52, cs=0.1, bc_y=0, bc_z=0,
+                  inlet_profile=1, u_in=0.04)
+        cyl, obj = (64.0, 63.5, 24.0), ((128, 0, 0), (128, 127, 111))
+    else:
+        kw = dict(stencil=0, precision=2, nx=8192, ny=2048, tau=0.6, u_in=0.04)
+        cyl, obj = (1024.0, 1023.5, 200.0), ((4096, 0, 0), (4096, 2047, 0))
+    outs = []
+    for policy in (H().CACHE_PLAIN, H().CACHE_AUTO):
+        G = H().Lattice(cache_policy=policy, **kw)
+        G.build_cylinder(*cyl)
+        G.init_equilibrium()
+        G.set_objective(O.OBJ_FFA, obj[0], obj[1], u0=0.04)
+        G.run_primal(5)
+        G.window_reset()
+        G.run_primal(4, accumulate=True)
+        G.solve_adjoint(H().SOURCE_MEAN, tau_adj=0.6, max_iters=4, turb=H().TURB_FROZEN)
+        outs.append((G.field(H().FIELD_U), G.window_objective(), G.gradient()))
+        G.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
 def test_lattice_above_the_threshold():
     """4096 x 2048 FP64: 8.4 M cells x (9 + 1) x 8 B = 671 MB > 256 MiB, so
     the automatic policy streams; it must reproduce the plain sweep."""
