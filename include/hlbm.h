@@ -304,6 +304,19 @@ hlbm_status hlbm_get_probe(hlbm_lattice lat, double* out, int64_t capacity, int6
  * 1) and of the adjoint sweep for this lattice's configuration. */
 hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* primal_window,
                                   double* adjoint);
+/* Bandwidth probe (a measurement, not a step of the method): n_launches
+ * back-to-back launches of a kernel that moves exactly the bytes of a plain
+ * primal sweep -- it reads every population slot and the porosity of each
+ * cell and writes the populations back unchanged -- on the same workgroups,
+ * tile order and addressing, with no arithmetic.  pattern 0: each cell's own
+ * slots (the even AA step's accesses); 1: interior cells read and write the
+ * odd step's upstream neighbour slots.  streaming != 0: nontemporal hints on
+ * every population access.  *us_per_launch receives the mean time per launch
+ * (HIP events on the lattice's stream around the launches; synchronises that
+ * stream).  The lattice state is unchanged.  Errors: INVALID (pattern,
+ * n_launches < 1, null output), DEVICE. */
+hlbm_status hlbm_copy_probe(hlbm_lattice lat, int32_t pattern, int32_t streaming, int64_t n_launches,
+                            double* us_per_launch);
 /* Changes the relaxation time, Smagorinsky constant and inflow speed of an
  * existing lattice (same validity rules as hlbm_create); the state, window
  * and adjoint are kept but the adjoint must be prepared again.  Lets a caller

@@ -868,6 +868,47 @@ __global__ __launch_bounds__(256) void k_primal_stream(const Geo g, const Coll c
 }
 
 // =========================================================================
+// bandwidth probe (measurement, outside the method): a plain primal step's
+// memory traffic -- every population slot and the porosity of each cell read,
+// the populations written back unchanged -- on the same 256-cell runs, tile
+// order and scalar-base addressing, without any arithmetic.  Its time per
+// launch is the practical ceiling of an in-place sweep on this lattice.
+// ODD: interior cells read and write the odd step's upstream slots (slot
+// opp(k) of the neighbour at x - xi_k), every other cell its own slots.
+// =========================================================================
+template <int Q, typename S, bool ODD, bool NT>
+__global__ __launch_bounds__(256) void k_copy_probe(const Geo g, S* __restrict__ A,
+                                                    const typename Prec<S>::Dd* __restrict__ dpor,
+                                                    int* __restrict__ sink) {
+  using L = Lat<Q>;
+  SWEEP_PROLOGUE_RUNS
+  if (!valid) return;
+  const auto d = at(dpor, tile_c0, tile_lo);
+  S v[Q];
+  const bool nb = ODD && interior_cell<Q>(g, x, y, z);
+  if (nb) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) v[k] = ld_stream<NT>(&at(A, L::opp[k] * g.plane + tile_c0 - nb_offset<Q>(g, k), tile_lo));
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) v[k] = ld_stream<NT>(&at(A, k * g.plane + tile_c0, tile_lo));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // opaque values: a store of the value just loaded from the same address
+  // would otherwise be removed as redundant
+#pragma unroll
+  for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(v[k]));
+  if (d < 0) *sink = 1;  // never taken (d is in [0, 1]); keeps the porosity load
+  if (nb) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, L::opp[k] * g.plane + tile_c0 - nb_offset<Q>(g, k), tile_lo), v[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, k * g.plane + tile_c0, tile_lo), v[k]);
+  }
+}
+
+// =========================================================================
 // forward tangent (App. C): one primal step of BGK-HLBM together with its
 // directional derivative fdot = (df/dd) v (FP64, no closure).  The tangent
 // lives in a second AA population array and follows exactly the same

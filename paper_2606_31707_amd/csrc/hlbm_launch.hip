@@ -458,6 +458,29 @@ hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev) {
   HLBM_DISPATCH(L, adjoint_gather_impl, L, out_dev);
 }
 
+template <int Q, typename S>
+static hipError_t copy_probe_impl(hlbm_lattice_s* L, int pattern, int streaming, int* sink) {
+  const Geo g = make_geo(L);
+  S* A = (S*)L->f;
+  const typename Prec<S>::Dd* dp = (const typename Prec<S>::Dd*)L->dpor;
+  const dim3 grid = sweep_grid(L);
+  if (pattern == 0) {
+    if (streaming)
+      k_copy_probe<Q, S, false, true><<<grid, kSweepBlock, 0, L->stream>>>(g, A, dp, sink);
+    else
+      k_copy_probe<Q, S, false, false><<<grid, kSweepBlock, 0, L->stream>>>(g, A, dp, sink);
+  } else {
+    if (streaming)
+      k_copy_probe<Q, S, true, true><<<grid, kSweepBlock, 0, L->stream>>>(g, A, dp, sink);
+    else
+      k_copy_probe<Q, S, true, false><<<grid, kSweepBlock, 0, L->stream>>>(g, A, dp, sink);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_copy_probe(hlbm_lattice_s* L, int pattern, int streaming, int* sink_dev) {
+  HLBM_DISPATCH(L, copy_probe_impl, L, pattern, streaming, sink_dev);
+}
+
 }  // namespace hlbm
 
 // =========================================================================

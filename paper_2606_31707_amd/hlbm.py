@@ -40,6 +40,7 @@ EXPORTS = [
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
     "hlbm_set_probe", "hlbm_get_probe", "hlbm_reconfigure", "hlbm_group_create", "hlbm_group_destroy",
     "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize", "hlbm_run_tangent",
+    "hlbm_copy_probe",
 ]
 
 GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
@@ -147,6 +148,7 @@ def load_library(path: str = LIB_PATH):
         "hlbm_get_probe": (i32, [vp, vp, i64, P(i64)]),
         "hlbm_run_tangent": (i32, [vp, vp, i64, i32, i64, i64, vp]),
         "hlbm_bytes_per_update": (i32, [vp, P(dbl), P(dbl), P(dbl)]),
+        "hlbm_copy_probe": (i32, [vp, i32, i32, i64, P(dbl)]),
         "hlbm_status_string": (C.c_char_p, [i32]),
         "hlbm_last_error": (C.c_char_p, []),
     }
@@ -375,6 +377,14 @@ class Lattice:
     def reconfigure(self, tau, cs, u_in):
         _check(self._lib.hlbm_reconfigure(self._h, tau, cs, u_in))
         self.desc.tau, self.desc.smagorinsky_cs, self.desc.u_in = tau, cs, u_in
+
+    def copy_probe(self, pattern=0, streaming=False, n_launches=20) -> float:
+        """Mean microseconds per launch of the bandwidth probe (a plain sweep's
+        bytes without arithmetic; pattern 0 own slots, 1 odd-step neighbours)."""
+        us = C.c_double()
+        _check(self._lib.hlbm_copy_probe(self._h, int(pattern), int(bool(streaming)), int(n_launches),
+                                         C.byref(us)))
+        return us.value
 
     def bytes_per_update(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()

@@ -23,6 +23,10 @@ Workload recipes (stand-ins for the paper's cylinder cases, Sec. 5):
                  lattice units = 0.792), drag plane x = 357 (1.7 m),
                  dissipation box x in [21, 482] (1.2 +- 1.1 m); T = 32 s =
                  42 336 steps.
+  grid2d_8192x4096  the vortex-street geometry on a grid whose populations
+                 exceed every cache (33.5 M cells, 2.4 GB FP64): D = 256 at
+                 (1024, 2047.5), u_max = 0.04, Re = 100, drag plane x_c + 5 D;
+                 the 2D roofline lattice of the sweep measurements.
 """
 from __future__ import annotations
 
@@ -124,6 +128,13 @@ def porous3d_re40() -> Workload:
                     83.5, bc_y=BC_PERIODIC, bc_z=BC_PERIODIC, objective=OBJ_FFA, lo=(357, 0, 0),
                     hi=(357, 167, 83), primal_steps=42336, d_solid=1.0 - tau * nu_l / k_l,
                     extra={"dissipation_box": ((21, 0, 0), (482, 167, 83))})
+
+
+def grid2d_8192x4096() -> Workload:
+    D, xc = 256.0, 1024.0
+    x = int(xc + 5 * D)
+    return Workload("grid2d_8192x4096", D2Q9, 8192, 4096, 1, 0.04, INLET_PARABOLIC, 100.0, D, xc, 2047.5,
+                    objective=OBJ_FFA, lo=(x, 0, 0), hi=(x, 4095, 0))
 
 
 def scaled(w: Workload, factor: float, name: str | None = None) -> Workload:

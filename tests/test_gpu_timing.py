@@ -55,3 +55,29 @@ def test_timing_leaves_results_unchanged():
         out.append((G.populations(), G.gradient()))
     for f, g in out[1:]:
         assert np.array_equal(f, out[0][0]) and np.array_equal(g, out[0][1])
+
+
+@pytest.mark.parametrize("stencil,prec", [(0, 0), (0, 2), (1, 1), (1, 2)])
+def test_copy_probe_leaves_the_state_unchanged(stencil, prec):
+    """The bandwidth probe reads and writes back every population slot (own
+    slots, or the odd step's neighbour slots): the lattice is bitwise
+    unchanged, in either AA parity, with and without streaming hints."""
+    say(f"copy probe stencil {stencil} precision {prec}")
+    if stencil == 0:
+        s = Spec(nx=133, ny=37, tau=0.56, u_in=0.05, cyl=(40.0, 18.0, 10.0))
+    else:
+        s = Spec(stencil=1, nx=37, ny=18, nz=9, tau=0.6, u_in=0.04, bc_y=0, bc_z=0, inlet_profile=1,
+                 cyl=(12.0, 8.5, 6.0))
+    G = make_gpu(s, precision=prec)
+    for steps in (6, 7):  # even and odd parity afterwards
+        G.run_primal(steps)
+        f0 = G.populations()
+        for pattern in (0, 1):
+            for nt in (False, True):
+                us = G.copy_probe(pattern, nt, 3)
+                assert 0.0 < us < 1e5
+        assert np.array_equal(G.populations(), f0)
+    with pytest.raises(H().HlbmError):
+        G.copy_probe(2, False, 1)
+    with pytest.raises(H().HlbmError):
+        G.copy_probe(0, False, 0)
