@@ -6,6 +6,16 @@ complex-step Jacobians.
 - the collision depends on f only through rho, j and sum xi xi f (the
   regularization discards the rest);
 - a third-order Hermite equilibrium at d = 1 is a fixed point;
+- the post-collision second moment is exactly
+  rho/3 I + rho u~u~ + (1 - 1/tau_eff) a2, a2 = sum xi xi f - rho/3 I - rho u~u~
+  (the regularized non-equilibrium part relaxes by 1 - 1/tau_eff);
+- the collision output is a Hermite series with the coefficients Eq. HRRLBM
+  names: rho, rho u~ + (1 - 1/tau)(1 - d) j, rho u~u~ + (1 - 1/tau) a2, and on
+  the supported third-order components rho u~_a^2 u~_b + (1 - 1/tau)
+  (2 u~_a a2_ab + u~_b a2_aa) (the recursive a3);
+- plane Poiseuille flow with the HRR collision: second differences of u_x
+  equal -G/nu exactly (the viscosity nu = (tau - 1/2)/3 of the relaxed
+  second moment);
 - the complex-step dC/df and dC/dd equal central finite differences, with and
   without the closure, frozen or differentiated;
 - a steady 3D channel flow with the HRR collision and the closure: the steady
@@ -57,6 +67,76 @@ def test_third_order_equilibrium_is_a_fixed_point(kind):
     f0 = O.hrr_collide_cell(kind, O.equilibrium(kind, 1.02, u), 1.0, 0.6)  # f^eq(rho, u) of the scheme
     f1 = O.hrr_collide_cell(kind, f0, 1.0, 0.6)
     assert np.abs(f1 - f0).max() < 1e-15
+
+
+def _state(kind, f, d):
+    c, w, _ = O.stencil(kind)
+    rho = f.sum()
+    ut = d * (c.T @ f) / rho
+    a2 = np.einsum("i,ia,ib->ab", f, c, c) - rho / 3.0 * np.eye(3) - rho * np.outer(ut, ut)
+    return c, w, rho, ut, a2
+
+
+@pytest.mark.parametrize("kind", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("cs", [0.0, 0.15])
+def test_second_moment_relaxes_exactly(kind, cs):
+    rng = np.random.default_rng(11)
+    D = 2 if kind == O.D2Q9 else 3
+    for d in (1.0, 0.65, 0.0):
+        f = _rand_f(kind, rng)
+        c, w, rho, ut, a2 = _state(kind, f, d)
+        tau = O.tau_eff(kind, f, 0.62, cs)
+        out = O.hrr_collide_cell(kind, f, d, 0.62, cs)
+        M2 = np.einsum("i,ia,ib->ab", out, c, c)
+        want = rho / 3.0 * np.eye(3) + rho * np.outer(ut, ut) + (1.0 - 1.0 / tau) * a2
+        assert np.abs(M2 - want)[:D, :D].max() < 1e-15
+        assert abs(a2[:D, :D]).max() > 1e-3  # a genuine non-equilibrium part
+
+
+@pytest.mark.parametrize("kind", [O.D2Q9, O.D3Q19])
+def test_output_is_the_regularized_hermite_series(kind):
+    """Fits the post-collision populations with the Hermite basis
+    {1, xi, H2, supported H_aab} (weighted by w_i, cs^2 = 1/3) and checks the
+    fitted coefficients against the HRRLBM relations."""
+    rng = np.random.default_rng(12)
+    D = 2 if kind == O.D2Q9 else 3
+    pairs = [(0, 1), (1, 0)] if D == 2 else [(0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)]
+    sym = [(a, b) for a in range(D) for b in range(a, D)]
+    for d in (1.0, 0.7):
+        f = _rand_f(kind, rng)
+        c, w, rho, ut, a2 = _state(kind, f, d)
+        tau = 0.58
+        out = O.hrr_collide_cell(kind, f, d, tau, 0.0)
+        cols = [w]
+        cols += [w * 3.0 * c[:, a] for a in range(D)]
+        cols += [w * 4.5 * (2.0 - (a == b)) * (c[:, a] * c[:, b] - (a == b) / 3.0) for a, b in sym]
+        cols += [w * 13.5 * c[:, b] * (c[:, a] ** 2 - 1.0 / 3.0) for a, b in pairs]
+        B = np.array(cols).T
+        coef, *_ = np.linalg.lstsq(B, out, rcond=None)
+        assert np.abs(B @ coef - out).max() < 1e-15  # the output lies in the span
+        om = 1.0 - 1.0 / tau
+        j = c.T @ f
+        want = [rho] + [rho * ut[a] + om * (1.0 - d) * j[a] for a in range(D)]
+        want += [rho * ut[a] * ut[b] + om * a2[a, b] for a, b in sym]
+        want += [rho * ut[a] ** 2 * ut[b] + om * (2.0 * ut[a] * a2[a, b] + ut[b] * a2[a, a]) for a, b in pairs]
+        assert np.abs(coef - np.array(want)).max() < 1e-14
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.3])
+def test_hrr_poiseuille_curvature_exact(tau):
+    H, G = 16, 1e-6
+    p = O.Params(nx=3, ny=H, tau=tau, bc_x=O.BC_PERIODIC, bc_y=O.BC_WALLS, force=(G, 0.0, 0.0),
+                 collision=O.COLL_HRR)
+    L = O.Lattice(p)
+    nu = (tau - 0.5) / 3.0
+    y = np.repeat(np.arange(H), 3)
+    u0 = np.zeros((3, L.n))
+    u0[0] = G / (2 * nu) * (y + 0.5) * (H - 0.5 - y)  # start near the solution (only shortens the run)
+    L.init_equilibrium(u=u0)
+    L.run_steady(400000, 1e-15, 500)
+    ux = L.moments()[1][0].reshape(H, 3)[:, 0]
+    d2 = ux[2:] - 2 * ux[1:-1] + ux[:-2]
+    assert np.abs(d2 * nu / G + 1.0).max() < 1e-9
 
 
 def _fd_jac(fun, f, h=1e-6):

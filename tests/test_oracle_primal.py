@@ -8,6 +8,11 @@
 - plane Poiseuille flow with halfway bounce-back: second differences equal
   -G/nu exactly, nu = (tau - 1/2)/3 (Sec. 2.1, viscosity relation), and the
   error to the continuum parabola is a uniform slip (second-order in H);
+- a forced channel filled with a uniform porous medium (Sec. 2.1, the
+  Brinkman-type equation the HLBM recovers, Eq. btnse): the steady profile
+  converges at second order to the continuum Brinkman solution
+  u = (G K / nu) [1 - cosh(y / sqrt K) / cosh(H / (2 sqrt K))] with
+  K = tau nu / (1 - d), the grid refined at a fixed Darcy number K / H^2;
 - the Smagorinsky closure: tau_eff solves tau = tau0 + 3 Cs^2 |S(tau)|
   (Sec. 2.2, Eqs. turbVisc, tauEff) and Cs = 0 gives plain BGK.
 """
@@ -124,6 +129,36 @@ def test_poiseuille_second_order():
         errs.append(np.abs(ux - ua).max() / ua.max())
     eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(eoc - 2.0) < 0.05), eoc
+
+
+def _brinkman_error(H, Da, tau, G):
+    """Relative max error of the converged porous channel (walls at y = -1/2
+    and H - 1/2, x periodic, uniform d) to the continuum Brinkman profile."""
+    nu = (tau - 0.5) / 3.0
+    K = Da * H * H
+    d = 1.0 - tau * nu / K  # Sec. 2.1: d = 1 - dx^2 tau nu / K
+    p = O.Params(nx=2, ny=H, tau=tau, bc_x=O.BC_PERIODIC, bc_y=O.BC_WALLS, force=(G, 0.0, 0.0))
+    L = O.Lattice(p)
+    L.set_porosity(np.full(L.n, d))
+    y = np.arange(H) - (H - 1) / 2.0
+    sk = np.sqrt(K)
+    ua = G * K / nu * (1.0 - np.cosh(y / sk) / np.cosh(H / (2.0 * sk)))
+    u0 = np.zeros((3, L.n))
+    u0[0] = np.repeat(ua, 2)  # start from the continuum profile (only shortens the run)
+    L.init_equilibrium(u=u0)
+    L.run_steady(400000, 1e-12, 500)
+    ux = L.moments()[1][0].reshape(H, 2)[:, 0]
+    assert np.abs(ux - ux[::-1]).max() < 1e-12 * ua.max()
+    return np.abs(ux - ua).max() / ua.max()
+
+
+def test_brinkman_channel_second_order():
+    """Darcy number 0.05 (H / sqrt K = 4.5: a flattened profile, far from the
+    parabola), tau = 0.8, H = 16, 32, 64."""
+    e = np.array([_brinkman_error(H, 0.05, 0.8, 1e-6) for H in (16, 32, 64)])
+    eoc = np.log2(e[:-1] / e[1:])
+    assert e[-1] < 1e-3, e
+    assert eoc[0] > 1.75 and 1.85 < eoc[1] < 2.1, eoc
 
 
 @pytest.mark.parametrize("kind", [O.D2Q9, O.D3Q19])
