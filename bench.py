@@ -406,13 +406,41 @@ def profile_commands(out: str):
     return cmds
 
 
+def _itanium_kernel(name: str):
+    """(base, template arguments) of a mangled hlbm kernel name (the trace
+    leaves names with _Float16 arguments mangled), or None."""
+    import re
+    m = re.match(r"_ZN4hlbm\d+(k_\w+?)I(.*?)EEv", name)
+    if not m:
+        return None
+    base, rest, args = m.group(1), m.group(2), []
+    tok = {"d": "double", "f": "float", "DF16_": "_Float16"}
+    while rest:
+        t = re.match(r"Li(\d+)E|Lb([01])E|(DF16_|d|f)", rest)
+        if not t:
+            return None
+        if t.group(1) is not None:
+            args.append(t.group(1))
+        elif t.group(2) is not None:
+            args.append("true" if t.group(2) == "1" else "false")
+        else:
+            args.append(tok[t.group(3)])
+        rest = rest[t.end():]
+    return base, args
+
+
 def kernel_kind(name: str):
-    """(kind, parity) of a sweep kernel's demangled name, or (None, None)."""
+    """(kind, parity) of a sweep kernel's (demangled or mangled) name, or
+    (None, None)."""
     import re
     m = re.match(r"(?:void )?hlbm::(k_\w+)<([^>]*)>", name)
-    if not m:
-        return None, None
-    base, targs = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    if m:
+        base, targs = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    else:
+        it = _itanium_kernel(name)
+        if it is None:
+            return None, None
+        base, targs = it
     if base in ("k_primal", "k_primal_stream"):
         return ("primal" if targs[3] == "0" else "primal_window"), targs[2]
     if base == "k_window_region":
@@ -441,7 +469,12 @@ def summarize_profiles(d: str):
 
     def short(name):
         name = name.replace("void ", "", 1)
-        return name.split("(")[0] if name.startswith("hlbm::") else name.split("(")[0][:60]
+        if name.startswith("hlbm::"):
+            return name.split("(")[0]
+        it = _itanium_kernel(name)
+        if it is not None:  # mangled (_Float16 arguments): written out the same way
+            return f"hlbm::{it[0]}<{', '.join(it[1])}>"
+        return name.split("(")[0][:60]
 
     cmds = profile_commands(d)
 

@@ -60,7 +60,8 @@ typedef enum {
   HLBM_E_INVALID = -1,      /* bad argument (size, range, NaN, null) */
   HLBM_E_OOM = -2,          /* device allocation failed */
   HLBM_E_STATE = -3,        /* call order violated (e.g. adjoint before objective) */
-  HLBM_E_DIVERGED = -4,     /* non-finite state or residual; outputs undefined */
+  HLBM_E_DIVERGED = -4,     /* non-finite state or residual, or a growing adjoint
+                               residual; outputs undefined */
   HLBM_E_DEVICE = -5        /* HIP runtime error */
 } hlbm_status;
 
@@ -181,9 +182,19 @@ typedef struct {
 hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out);
 /* Free every device buffer of the handle (synchronises its stream). */
 void hlbm_destroy(hlbm_lattice lat);
-/* Device bytes a lattice needs with the window and adjoint buffers. */
+/* Device bytes a lattice of this descriptor holds at most for one query:
+ * populations, porosity, outlet values, reduction partials and the steady-
+ * check snapshot; the objective's region buffers for region_cells cells of
+ * kind `objective` (0 cells: no objective); with_window != 0 the FP64 window
+ * sums; with_adjoint != 0 the adjoint populations, frozen data, gradient data
+ * and residual snapshot.  A velocity probe and the forward tangent's buffers
+ * are not included.  Equals hlbm_device_bytes after such a query (primal
+ * with steady checks and window, adjoint with residual checks, gradient).
+ * Errors: INVALID (descriptor, region_cells outside [0, n], kind). */
 hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int with_adjoint,
-                                 uint64_t* bytes);
+                                 int64_t region_cells, int32_t objective, uint64_t* bytes);
+/* Device bytes the handle holds now (every buffer it has allocated). */
+hlbm_status hlbm_device_bytes(hlbm_lattice lat, uint64_t* bytes);
 
 /* ---- geometry and initial state (rows a1, a2) --------------------------- */
 
@@ -262,7 +273,14 @@ hlbm_status hlbm_run_tangent(hlbm_lattice lat, const double* v, int64_t n, int32
 
 /* ---- adjoint and gradient (rows a7, a8, a9) ------------------------------ */
 
-/* Freeze the Jacobian data (row a7) and iterate the adjoint sweep (row a8).
+/* Freeze the Jacobian data (row a7) and iterate the adjoint sweep (row a8)
+ * until its variables are steady (Algorithm 1).  With tol > 0, every
+ * check_every iterations the relative residual max|phi_k - phi_(k-M)| /
+ * max|phi_k| is formed in FP64: at most tol ends the call with OK; a
+ * non-finite value, or a residual above 1e3 times the smallest residual of
+ * this call, ends it with DIVERGED (outputs undefined); max_iters without
+ * either gives W_NOT_CONVERGED (outputs valid, report->residual the last
+ * residual).  tol = 0 runs max_iters iterations and checks nothing.
  * Returns STATE without an objective (or without a window for MEAN, or
  * without tracked mean populations for the differentiated closure or for a
  * MEAN source with the HRR collision, whose frozen data include the mean

@@ -24,6 +24,9 @@ class Plan:
     (stopping early once the steady criterion steady_tol is met; 0 runs all
     steps).  window_steps > 0: spin-up of primal_steps - window_steps steps,
     then the mean of J over window_steps steps (mean-flow adjoint).
+    initial_populations: the state the primal starts from (q x n float64,
+    canonical layout, host or device); None starts from the equilibrium
+    f^eq(1, d u_in) of the lattice's inlet profile.
     """
     primal_steps: int = 20000
     window_steps: int = 0
@@ -33,6 +36,7 @@ class Plan:
     adjoint_tol: float = 0.0
     tau_adj: float = 0.0
     turb: int = H.TURB_FROZEN
+    initial_populations: object = None
 
 
 def make_lattice(stencil=H.D2Q9, precision=H.FP64, **kw) -> H.Lattice:
@@ -48,7 +52,10 @@ class HLBMObjective(torch.autograd.Function):
             raise ValueError("porosity must be a CUDA tensor")
         dd = d.detach().to(torch.float64).contiguous().view(-1)
         lat.set_porosity(dd)
-        lat.init_equilibrium()
+        if plan.initial_populations is not None:
+            lat.set_populations(plan.initial_populations)
+        else:
+            lat.init_equilibrium()
         if plan.window_steps > 0:
             lat.run_primal(plan.primal_steps - plan.window_steps)
             lat.run_primal(plan.window_steps, accumulate=True)
@@ -57,11 +64,18 @@ class HLBMObjective(torch.autograd.Function):
             lat.run_primal(plan.primal_steps, steady_tol=plan.steady_tol, check_every=plan.check_every)
             J = lat.objective(0)
         ctx.lat, ctx.plan, ctx.shape = lat, plan, d.shape
+        # the backward adjoint runs on the state the lattice holds then: it
+        # must still be the one this forward produced
+        ctx.generation = lat.generation
         return torch.tensor(J, dtype=torch.float64, device=d.device)
 
     @staticmethod
     def backward(ctx, gJ: torch.Tensor):
         lat, plan = ctx.lat, ctx.plan
+        if lat.generation != ctx.generation:
+            raise RuntimeError("the lattice was changed (porosity, state or primal steps) after this objective's "
+                               "forward pass; its backward would differentiate another state. Run backward first, "
+                               "or give each objective evaluation its own lattice")
         source = H.SOURCE_MEAN if plan.window_steps > 0 else H.SOURCE_STEADY
         lat.solve_adjoint(source, tau_adj=plan.tau_adj, turb=plan.turb, max_iters=plan.adjoint_iters,
                           tol=plan.adjoint_tol, check_every=max(2, plan.check_every))

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hlbm_internal.hpp"
+#include "hlbm_stop.hpp"
 
 using namespace hlbm;
 
@@ -63,6 +64,20 @@ hlbm_status dev_alloc(void** p, size_t bytes) {
 
 void dev_free(void* p) {
   if (p) (void)hipFree(p);
+}
+
+// Buffers owned by a lattice are allocated and freed through these, which
+// keep the handle's record of its device memory.
+hlbm_status lat_alloc(hlbm_lattice_s* L, void** p, size_t bytes) {
+  if (*p) return HLBM_OK;
+  hlbm_status s = dev_alloc(p, bytes);
+  if (s == HLBM_OK) L->allocs[*p] = bytes ? bytes : 256;
+  return s;
+}
+void lat_free(hlbm_lattice_s* L, void* p) {
+  if (!p) return;
+  L->allocs.erase(p);
+  dev_free(p);
 }
 
 int q_of(int stencil) { return stencil == HLBM_D2Q9 ? 9 : 19; }
@@ -148,11 +163,11 @@ hlbm_status ensure_window(hlbm_lattice_s* L) {
   const int64_t P = L->plane;
   hlbm_status s;
   bool fresh = L->acc_rho == nullptr;
-  if ((s = dev_alloc((void**)&L->acc_rho, sizeof(double) * P)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->acc_j, sizeof(double) * P * L->dim)) != HLBM_OK) return s;
-  if (L->desc.track_mean_populations && (s = dev_alloc((void**)&L->acc_f, sizeof(double) * P * L->q)) != HLBM_OK)
+  if ((s = lat_alloc(L, (void**)&L->acc_rho, sizeof(double) * P)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->acc_j, sizeof(double) * P * L->dim)) != HLBM_OK) return s;
+  if (L->desc.track_mean_populations && (s = lat_alloc(L, (void**)&L->acc_f, sizeof(double) * P * L->q)) != HLBM_OK)
     return s;
-  if (L->desc.smagorinsky_cs > 0.0 && (s = dev_alloc((void**)&L->acc_tau, sizeof(double) * P)) != HLBM_OK) return s;
+  if (L->desc.smagorinsky_cs > 0.0 && (s = lat_alloc(L, (void**)&L->acc_tau, sizeof(double) * P)) != HLBM_OK) return s;
   if (fresh) {
     HIP_TRY(hipMemsetAsync(L->acc_rho, 0, sizeof(double) * P, L->stream));
     HIP_TRY(hipMemsetAsync(L->acc_j, 0, sizeof(double) * P * L->dim, L->stream));
@@ -164,10 +179,10 @@ hlbm_status ensure_window(hlbm_lattice_s* L) {
 
 hlbm_status ensure_partials(hlbm_lattice_s* L, int64_t nvals) {
   if (L->red_cap >= nvals) return HLBM_OK;
-  dev_free(L->red);
+  lat_free(L, L->red);
   L->red = nullptr;
   L->red_cap = 0;
-  hlbm_status s = dev_alloc((void**)&L->red, sizeof(double) * (size_t)nvals);
+  hlbm_status s = lat_alloc(L, (void**)&L->red, sizeof(double) * (size_t)nvals);
   if (s == HLBM_OK) L->red_cap = nvals;
   return s;
 }
@@ -285,27 +300,47 @@ const char* hlbm_status_string(hlbm_status s) {
   return "unknown status";
 }
 
-hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int with_adjoint, uint64_t* bytes) {
+hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int with_adjoint, int64_t region_cells,
+                                 int32_t objective, uint64_t* bytes) {
   hlbm_status s = validate_desc(desc);
   if (s != HLBM_OK) return s;
   if (!bytes) return fail(HLBM_E_INVALID, "null output");
-  const int q = q_of(desc->stencil), dim = dim_of(desc->stencil);
   const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
-  const int64_t P = plane_stride(n, ssize_of(desc->precision)), G = round_up((int64_t)desc->ny * desc->nz, 128);
-  uint64_t b = (uint64_t)P * (q * ssize_of(desc->precision) + dsize_of(desc->precision)) +
-               (uint64_t)G * q * ssize_of(desc->precision);
+  if (region_cells < 0 || region_cells > n) return fail(HLBM_E_INVALID, "region_cells outside [0, n]");
+  if (objective < HLBM_OBJ_FFA || objective > HLBM_OBJ_MEA) return fail(HLBM_E_INVALID, "bad objective kind");
+  const int q = q_of(desc->stencil), dim = dim_of(desc->stencil), ncoef = ncoef_of(desc->stencil);
+  const uint64_t P = (uint64_t)plane_stride(n, ssize_of(desc->precision));
+  const uint64_t G = (uint64_t)round_up((int64_t)desc->ny * desc->nz, 128);
+  const uint64_t ss = ssize_of(desc->precision), ds = dsize_of(desc->precision), as = asize_of(desc->precision);
+  const uint64_t blocks = (uint64_t)((desc->nx + BX - 1) / BX) * ((desc->ny + BY - 1) / BY) * desc->nz;
+  // populations, porosity, outlet values, reduction partials, steady-check snapshot
+  uint64_t b = P * (q * ss + ds) + G * q * ss + 8 * (2 * blocks + 8) + 8 * P * dim;
+  if (region_cells > 0) {  // objective terms and adjoint source over the region
+    const uint64_t rp = (uint64_t)round_up(region_cells, 128);
+    b += 2 * 8 * rp * ncoef;
+    if (objective == HLBM_OBJ_MEA) b += rp + 8 * q * rp;  // surface flags and source
+  }
   if (with_window) {
-    b += (uint64_t)P * 8 * (1 + dim);
-    if (desc->track_mean_populations) b += (uint64_t)P * 8 * q;
-    if (desc->smagorinsky_cs > 0) b += (uint64_t)P * 8;
+    b += P * 8 * (1 + dim);
+    if (desc->track_mean_populations) b += P * 8 * q;
+    if (desc->smagorinsky_cs > 0) b += P * 8;
   }
   if (with_adjoint) {
-    const size_t as = asize_of(desc->precision);
-    b += (uint64_t)P * as * q;                                   // phi
-    b += (uint64_t)P * as * (dim + 2 + q + nb_of(desc->stencil)); // frozen coefficients
-    b += (uint64_t)P * 8 * (dim + 2);                            // gradient data
-    b += (uint64_t)G * (8 * (1 + dim) + 2 * as * q);
+    b += P * as * q;                                    // phi
+    b += P * as * (dim + 2 + q + nb_of(desc->stencil)); // frozen coefficients
+    b += P * 8 * (dim + 2);                             // gradient data
+    b += G * (8 * (1 + dim) + 2 * as * q);              // outlet data, outlet adjoint values
+    b += P * as * q;                                    // residual snapshot
   }
+  *bytes = b;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_device_bytes(hlbm_lattice L, uint64_t* bytes) {
+  CHECK_LAT(L);
+  if (!bytes) return fail(HLBM_E_INVALID, "null output");
+  uint64_t b = 0;
+  for (const auto& kv : L->allocs) b += kv.second;
   *bytes = b;
   return HLBM_OK;
 }
@@ -345,9 +380,9 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
     hlbm_destroy(L);
     return st;
   };
-  if ((s = dev_alloc(&L->f, L->ssize * L->q * L->plane)) != HLBM_OK) return bail(s);
-  if ((s = dev_alloc(&L->dpor, L->dsize * L->plane)) != HLBM_OK) return bail(s);
-  if ((s = dev_alloc(&L->ghost, L->ssize * L->q * L->gplane)) != HLBM_OK) return bail(s);
+  if ((s = lat_alloc(L, &L->f, L->ssize * L->q * L->plane)) != HLBM_OK) return bail(s);
+  if ((s = lat_alloc(L, &L->dpor, L->dsize * L->plane)) != HLBM_OK) return bail(s);
+  if ((s = lat_alloc(L, &L->ghost, L->ssize * L->q * L->gplane)) != HLBM_OK) return bail(s);
   if ((s = ensure_partials(L, 2 * n_blocks(L) + 8)) != HLBM_OK) return bail(s);
   if (hipHostMalloc((void**)&L->red_host, 4 * sizeof(double)) != hipSuccess)
     return bail(fail(HLBM_E_OOM, "pinned host allocation failed"));
@@ -510,10 +545,10 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
   for (int a = 0; a < 3; ++a) rn[a] = hi[a] - lo[a] + 1;
   const int64_t rp = round_up((int64_t)rn[0] * rn[1] * rn[2], 128);
   if (rp > L->rplane) {
-    dev_free(L->acc_obj);
-    dev_free(L->src);
-    dev_free(L->mea_flag);
-    dev_free(L->mea_src);
+    lat_free(L, L->acc_obj);
+    lat_free(L, L->src);
+    lat_free(L, L->mea_flag);
+    lat_free(L, L->mea_src);
     L->mea_src = nullptr;
     L->acc_obj = nullptr;
     L->src = nullptr;
@@ -521,17 +556,17 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
     L->rplane = 0;
   }
   hlbm_status s;
-  if ((s = dev_alloc((void**)&L->acc_obj, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->src, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->acc_obj, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->src, sizeof(double) * rp * L->ncoef)) != HLBM_OK) return s;
   L->mea_dirty = 1;
   L->rplane = rp > L->rplane ? rp : L->rplane;
   if (kind == HLBM_OBJ_MEA) {  // sized for the plane stride the kernels index with
-    dev_free(L->mea_flag);
-    dev_free(L->mea_src);
+    lat_free(L, L->mea_flag);
+    lat_free(L, L->mea_src);
     L->mea_flag = nullptr;
     L->mea_src = nullptr;
-    if ((s = dev_alloc((void**)&L->mea_flag, L->rplane)) != HLBM_OK) return s;
-    if ((s = dev_alloc((void**)&L->mea_src, sizeof(double) * L->q * L->rplane)) != HLBM_OK) return s;
+    if ((s = lat_alloc(L, (void**)&L->mea_flag, L->rplane)) != HLBM_OK) return s;
+    if ((s = lat_alloc(L, (void**)&L->mea_src, sizeof(double) * L->q * L->rplane)) != HLBM_OK) return s;
   }
   L->obj_kind = kind;
   for (int a = 0; a < 3; ++a) {
@@ -592,7 +627,7 @@ hlbm_status hlbm_set_probe(hlbm_lattice L, int32_t x, int32_t y, int32_t z, int6
   if (capacity < 0) return fail(HLBM_E_INVALID, "capacity must be >= 0");
   if (capacity == 0) {
     HIP_TRY(hipStreamSynchronize(L->stream));
-    dev_free(L->probe_buf);
+    lat_free(L, L->probe_buf);
     L->probe_buf = nullptr;
     L->probe_cap = L->probe_n = 0;
     L->probe_cell = -1;
@@ -602,9 +637,9 @@ hlbm_status hlbm_set_probe(hlbm_lattice L, int32_t x, int32_t y, int32_t z, int6
     return fail(HLBM_E_INVALID, "probe outside the lattice");
   if (capacity != L->probe_cap) {
     HIP_TRY(hipStreamSynchronize(L->stream));
-    dev_free(L->probe_buf);
+    lat_free(L, L->probe_buf);
     L->probe_buf = nullptr;
-    hlbm_status s = dev_alloc((void**)&L->probe_buf, sizeof(double) * (size_t)capacity);
+    hlbm_status s = lat_alloc(L, (void**)&L->probe_buf, sizeof(double) * (size_t)capacity);
     if (s != HLBM_OK) return s;
   }
   L->probe_cap = capacity;
@@ -642,7 +677,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     if ((s = ensure_window(L)) != HLBM_OK) return s;
   }
   if (steady_tol > 0.0) {
-    if ((s = dev_alloc((void**)&L->usnap, sizeof(double) * L->plane * L->dim)) != HLBM_OK) return s;
+    if ((s = lat_alloc(L, (void**)&L->usnap, sizeof(double) * L->plane * L->dim)) != HLBM_OK) return s;
   }
   const int64_t nb = n_blocks(L);
   // snapshot of u at the start of a steady run
@@ -703,14 +738,14 @@ hlbm_status hlbm_run_tangent(hlbm_lattice L, const double* v, int64_t n, int32_t
   if (nrec > 0 && !out) return fail(HLBM_E_INVALID, "null output");
   hlbm_status s;
   if ((s = ensure_mea(L)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->tan_f, sizeof(double) * L->q * L->plane)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->tan_ghost, sizeof(double) * L->q * L->gplane)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->tan_v, sizeof(double) * L->plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->tan_f, sizeof(double) * L->q * L->plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->tan_ghost, sizeof(double) * L->q * L->gplane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->tan_v, sizeof(double) * L->plane)) != HLBM_OK) return s;
   if (nrec > L->tan_rec_cap) {
-    dev_free(L->tan_rec);
+    lat_free(L, L->tan_rec);
     L->tan_rec = nullptr;
     L->tan_rec_cap = 0;
-    if ((s = dev_alloc((void**)&L->tan_rec, sizeof(double) * 2 * nrec)) != HLBM_OK) return s;
+    if ((s = lat_alloc(L, (void**)&L->tan_rec, sizeof(double) * 2 * nrec)) != HLBM_OK) return s;
     L->tan_rec_cap = nrec;
   }
   HIP_TRY(hipMemcpyAsync(L->tan_v, v, sizeof(double) * L->n,
@@ -784,13 +819,13 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
   const size_t as = L->asize;
   hlbm_status s;
   const int nprep = L->dim + 2 + L->q + L->nb;
-  if ((s = dev_alloc(&L->phi, as * L->q * plane)) != HLBM_OK) return s;
-  if ((s = dev_alloc(&L->prep, as * nprep * plane)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->gdat, sizeof(double) * (L->dim + 2) * plane)) != HLBM_OK) return s;
-  if ((s = dev_alloc((void**)&L->oprep, sizeof(double) * (1 + L->dim) * L->gplane)) != HLBM_OK) return s;
-  if ((s = dev_alloc(&L->pv[0], as * L->q * L->gplane)) != HLBM_OK) return s;
-  if ((s = dev_alloc(&L->pv[1], as * L->q * L->gplane)) != HLBM_OK) return s;
-  if (o->tol > 0.0 && (s = dev_alloc(&L->snap, as * L->q * plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, &L->phi, as * L->q * plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, &L->prep, as * nprep * plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->gdat, sizeof(double) * (L->dim + 2) * plane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, (void**)&L->oprep, sizeof(double) * (1 + L->dim) * L->gplane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, &L->pv[0], as * L->q * L->gplane)) != HLBM_OK) return s;
+  if ((s = lat_alloc(L, &L->pv[1], as * L->q * L->gplane)) != HLBM_OK) return s;
+  if (o->tol > 0.0 && (s = lat_alloc(L, &L->snap, as * L->q * plane)) != HLBM_OK) return s;
   L->nprep = nprep;
   const bool turb_diff = smag && o->turb == HLBM_TURB_DIFFERENTIATED;
   if (o->restart || !L->adj_ready || L->adj_diff != (int)turb_diff) {
@@ -819,6 +854,7 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
   }
   int64_t done = 0;
   bool converged = false;
+  double min_res = HUGE_VAL;
   while (done < iters) {
     int64_t chunk = iters - done;
     if (o->tol > 0.0 && chunk > M) chunk = M;
@@ -834,12 +870,16 @@ hlbm_status hlbm_solve_adjoint(hlbm_lattice L, const hlbm_adjoint_opts* o, hlbm_
       HIP_TRY(launch_adjoint_residual(L, 0, L->red, &nbl));
       double mm[2];
       if ((s = reduce_to_host(L, nbl, 1, mm)) != HLBM_OK) return s;
-      if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) {
-        if (rep) rep->iters = done;
-        return fail(HLBM_E_DIVERGED, "non-finite adjoint after %lld iterations", (long long)L->adj_iters);
+      const StopDecision dec = adjoint_stop(mm[0], mm[1], o->tol, &min_res, &res);
+      if (dec == STOP_DIVERGED) {
+        if (rep) {
+          rep->iters = done;
+          rep->residual = res;
+        }
+        return fail(HLBM_E_DIVERGED, "adjoint diverged after %lld iterations (residual %g, smallest %g)",
+                    (long long)L->adj_iters, res, min_res);
       }
-      res = mm[1] > 0.0 ? mm[0] / mm[1] : mm[0];
-      if (res <= o->tol) {
+      if (dec == STOP_CONVERGED) {
         converged = true;
         break;
       }
@@ -996,7 +1036,7 @@ extern "C" hlbm_status hlbm_reconfigure(hlbm_lattice L, double tau, double cs, d
   hlbm_status s = validate_desc(&d);
   if (s != HLBM_OK) return s;
   if (cs > 0.0 && L->desc.smagorinsky_cs == 0.0 && L->acc_rho && !L->acc_tau) {
-    if ((s = dev_alloc((void**)&L->acc_tau, sizeof(double) * L->plane)) != HLBM_OK) return s;
+    if ((s = lat_alloc(L, (void**)&L->acc_tau, sizeof(double) * L->plane)) != HLBM_OK) return s;
     HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * L->plane, L->stream));
   }
   L->desc.tau = tau;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <unordered_map>
+
 #include "../../include/hlbm.h"
 #include "hlbm_device.hpp"
 
@@ -94,6 +96,9 @@ struct hlbm_lattice_s {
   int64_t probe_cell = -1;
   double* probe_buf = nullptr;
   int64_t probe_cap = 0, probe_n = 0;
+
+  // every device buffer the handle owns, with its size (hlbm_device_bytes)
+  std::unordered_map<void*, size_t> allocs;
 };
 
 namespace hlbm {

@@ -40,7 +40,7 @@ EXPORTS = [
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
     "hlbm_set_probe", "hlbm_get_probe", "hlbm_reconfigure", "hlbm_group_create", "hlbm_group_destroy",
     "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize", "hlbm_run_tangent",
-    "hlbm_copy_probe",
+    "hlbm_copy_probe", "hlbm_device_bytes",
 ]
 
 GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
@@ -120,7 +120,8 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "hlbm_create": (i32, [P(Desc), P(vp)]),
         "hlbm_destroy": (None, [vp]),
-        "hlbm_footprint_bytes": (i32, [P(Desc), i32, i32, P(C.c_uint64)]),
+        "hlbm_footprint_bytes": (i32, [P(Desc), i32, i32, i64, i32, P(C.c_uint64)]),
+        "hlbm_device_bytes": (i32, [vp, P(C.c_uint64)]),
         "hlbm_set_porosity": (i32, [vp, vp, i64, i32]),
         "hlbm_build_cylinder": (i32, [vp, dbl, dbl, dbl, vp, i64, i32, i32, dbl, dbl]),
         "hlbm_init_equilibrium": (i32, [vp, dbl, vp, i64, i32]),
@@ -216,10 +217,13 @@ def make_desc(stencil=D2Q9, precision=FP64, nx=32, ny=16, nz=1, tau=0.8, cs=0.0,
     return d
 
 
-def footprint_bytes(desc: Desc, with_window=True, with_adjoint=True) -> int:
+def footprint_bytes(desc: Desc, with_window=True, with_adjoint=True, region_cells=0, objective=OBJ_FFA) -> int:
+    """Device bytes one query on a lattice of this descriptor holds at most
+    (objective region of region_cells cells of the given kind)."""
     lib = load_library()
     out = C.c_uint64()
-    _check(lib.hlbm_footprint_bytes(C.byref(desc), int(with_window), int(with_adjoint), C.byref(out)))
+    _check(lib.hlbm_footprint_bytes(C.byref(desc), int(with_window), int(with_adjoint), int(region_cells),
+                                    int(objective), C.byref(out)))
     return int(out.value)
 
 
@@ -234,6 +238,10 @@ class Lattice:
         self._h = h
         self.q = 9 if self.desc.stencil == D2Q9 else 19
         self.n = self.desc.nx * self.desc.ny * self.desc.nz
+        # bumped by every call that changes the porosity, the primal state,
+        # the window or the objective (the adjoint of a forward pass is only
+        # valid while it is unchanged)
+        self.generation = 0
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -246,19 +254,23 @@ class Lattice:
 
     # ---- geometry / state
     def set_porosity(self, d):
+        self.generation += 1
         p, n, mem, _keep = _arr_in(d, self.n)
         _check(self._lib.hlbm_set_porosity(self._h, p, n, mem))
 
     def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0, d_solid=0.0):
+        self.generation += 1
         p, n, mem, _keep = _arr_in(noise, self.n)
         _check(self._lib.hlbm_build_cylinder(self._h, xc, yc, D, p, n if noise is not None else 0,
                                              mem, noise_mode, box_half, d_solid))
 
     def init_equilibrium(self, rho0=1.0, u=None):
+        self.generation += 1
         p, n, mem, _keep = _arr_in(u, 3 * self.n)
         _check(self._lib.hlbm_init_equilibrium(self._h, rho0, p, n, mem))
 
     def set_populations(self, f):
+        self.generation += 1
         p, n, mem, _keep = _arr_in(f, self.q * self.n)
         _check(self._lib.hlbm_set_populations(self._h, p, n, mem))
 
@@ -283,11 +295,13 @@ class Lattice:
 
     # ---- objective / primal / window
     def set_objective(self, kind, lo, hi, u0=0.0, p0=1.0 / 3.0):
+        self.generation += 1
         lo3 = (C.c_int32 * 3)(*(list(lo) + [0] * (3 - len(lo))))
         hi3 = (C.c_int32 * 3)(*(list(hi) + [0] * (3 - len(hi))))
         _check(self._lib.hlbm_set_objective(self._h, kind, lo3, hi3, u0, p0))
 
     def run_primal(self, n_steps, accumulate=False, steady_tol=0.0, check_every=100):
+        self.generation += 1
         done = C.c_int64()
         st = self._lib.hlbm_run_primal(self._h, int(n_steps), int(bool(accumulate)), steady_tol,
                                        int(check_every), C.byref(done))
@@ -300,6 +314,7 @@ class Lattice:
     def run_tangent(self, v, n_steps, record_every=1):
         """Forward tangent along v from the current state: returns an array
         [records, 2] of (J(t), dJ(t)/dd . v)."""
+        self.generation += 1
         p, n, mem, _keep = _arr_in(v, self.n)
         nrec = int(n_steps) // int(record_every)
         out = np.zeros(2 * max(nrec, 1))
@@ -308,6 +323,7 @@ class Lattice:
         return out[: 2 * nrec].reshape(nrec, 2)
 
     def window_reset(self):
+        self.generation += 1
         _check(self._lib.hlbm_window_reset(self._h))
 
     def window_count(self) -> int:
@@ -375,8 +391,15 @@ class Lattice:
         return out[: cnt.value].copy()
 
     def reconfigure(self, tau, cs, u_in):
+        self.generation += 1
         _check(self._lib.hlbm_reconfigure(self._h, tau, cs, u_in))
         self.desc.tau, self.desc.smagorinsky_cs, self.desc.u_in = tau, cs, u_in
+
+    def device_bytes(self) -> int:
+        """Device bytes this lattice holds now."""
+        out = C.c_uint64()
+        _check(self._lib.hlbm_device_bytes(self._h, C.byref(out)))
+        return int(out.value)
 
     def copy_probe(self, pattern=0, streaming=False, n_launches=20) -> float:
         """Mean microseconds per launch of the bandwidth probe (a plain sweep's

@@ -20,7 +20,7 @@ import heapq
 import math
 import time
 from collections import OrderedDict, deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -289,9 +289,17 @@ class GPUBackend:
                            inlet_profile=H.INLET_PARABOLIC, u_in=q.u_max, stream=stream)
 
     def footprint(self, q: Query) -> int:
+        """Device bytes of a pooled lattice of the query's shape: its largest
+        query (the window, the adjoint and the larger of the two objective
+        regions, which a pooled lattice keeps once it has held it)."""
         k = self._key(q)
         if k not in self._fp:
-            self._fp[k] = self.H.footprint_bytes(self._desc(q, None), True, True)
+            worst = 0
+            for kind in (OBJ_FFA, OBJ_DISS):
+                lo, hi = replace(q, objective=kind).region()
+                cells = (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1)
+                worst = max(worst, self.H.footprint_bytes(self._desc(q, None), True, True, cells, kind))
+            self._fp[k] = worst
         return self._fp[k]
 
     def reserve(self, q: Query, cap: int) -> bool:

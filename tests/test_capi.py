@@ -86,3 +86,17 @@ def test_product_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", text, flags=re.M), f
                 assert "hlbm_oracle" not in text, f
+
+
+def test_footprint_counts_the_objective_region_without_gpu():
+    from paper_2606_31707_amd import hlbm as H
+    d = H.make_desc(nx=220, ny=41)
+    base = H.footprint_bytes(d, True, True)
+    diss = H.footprint_bytes(d, True, True, 200 * 41, H.OBJ_DISS)
+    mea = H.footprint_bytes(d, True, True, 200 * 41, H.OBJ_MEA)
+    rp = -(-200 * 41 // 128) * 128
+    assert diss - base == 2 * 8 * 8 * rp          # two arrays of 8 FP64 coefficients per region cell
+    assert mea - diss == rp + 8 * 9 * rp           # surface flags and the constant source
+    for bad in [(-1, H.OBJ_DISS), (220 * 41 + 1, H.OBJ_DISS), (10, 7)]:
+        with pytest.raises(H.HlbmError):
+            H.footprint_bytes(d, True, True, *bad)

@@ -102,3 +102,46 @@ def test_empty_tangent_record_and_empty_window():
     with pytest.raises(H().HlbmError) as e:
         G.window_objective()
     assert e.value.status == H().E_STATE
+
+
+@pytest.mark.gpu
+def test_adjoint_not_converged_within_max_iters():
+    """A tolerance the iteration budget cannot reach: W_NOT_CONVERGED, the
+    iterations done and the last residual reported, the outputs valid (equal
+    to a plain fixed-count run of the same length)."""
+    s = _channel()
+    say("edge: adjoint not converged")
+    G = make_gpu(s)
+    G.run_primal(300)
+    it, res, st = G.solve_adjoint(H().SOURCE_STEADY, max_iters=40, tol=1e-14, check_every=10)
+    assert st == H().W_NOT_CONVERGED and it == 40 and 1e-14 < res < 1.0
+    g1 = G.gradient()
+    it2, res2, st2 = G.solve_adjoint(H().SOURCE_STEADY, max_iters=40)
+    assert st2 == H().OK and it2 == 40 and res2 == -1.0
+    assert np.array_equal(G.gradient(), g1)
+
+
+@pytest.mark.gpu
+def test_non_finite_state_is_reported_as_diverged():
+    """A host-supplied state with one non-finite population: the primal's
+    steady check and the adjoint's residual check both end the call with
+    E_DIVERGED (every kernel runs to completion on the NaN values)."""
+    s = _channel()
+    say("edge: diverged")
+    G = make_gpu(s)
+    G.run_primal(50)
+    f = G.populations()
+    f[3, 20 + 67 * 9] = np.nan
+    G.set_populations(f)
+    with pytest.raises(H().HlbmError) as e:
+        G.run_primal(40, steady_tol=1e-10, check_every=10)
+    assert e.value.status == H().E_DIVERGED
+    G.set_populations(f)
+    with pytest.raises(H().HlbmError) as e:
+        G.solve_adjoint(H().SOURCE_STEADY, max_iters=40, tol=1e-10, check_every=10)
+    assert e.value.status == H().E_DIVERGED
+    # the lattice is still usable: a finite state runs normally again
+    f[3, 20 + 67 * 9] = f[3, 21 + 67 * 9]
+    G.set_populations(f)
+    G.run_primal(10)
+    assert np.isfinite(G.populations()).all()

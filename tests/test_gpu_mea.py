@@ -82,4 +82,5 @@ def test_mea_mean_flow_and_porosity_change():
     e_phi = rel_err(G.adjoint(), L.adjoint(), state_mask(s))
     e_g = rel_err(G.gradient(), L.gradient())
     print(f"mea mean adjoint parity: phi {e_phi:.3e} gradient {e_g:.3e}", flush=True)
-    assert e_phi < 1e-11 and e_g < 1e-11
+    # J_MEA is linear in f (no Pi): the mean-flow bound is the steady one
+    assert e_phi < 1e-12 and e_g < 1e-12

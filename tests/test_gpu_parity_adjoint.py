@@ -8,7 +8,11 @@ relaxation time depend on Pi, a ~1e-5 difference of O(0.1) populations, so
 rounding-level differences of two independently computed primal states
 (~1e-14) would otherwise be amplified ~1e3 in the adjoint source.  Mean-flow
 cases re-synchronise the state at the start of the window; their remaining
-window-rounding differences are amplified the same way, hence TOL_MEAN."""
+window-rounding differences are amplified the same way where the source or
+the relaxation time depends on Pi (J_DISS, the closure): TOL_MEAN there.  The
+drag objectives (J_FFA, J_MEA) read no Pi and keep TOL on the mean flow.  The
+amplification is a property of the method, measured on the oracle alone in
+tests/test_oracle_sensitivity.py."""
 import numpy as np
 import pytest
 
@@ -98,7 +102,7 @@ def test_mean_flow_adjoint(kind):
     L.adjoint_prepare(1, 0.6)
     L.adjoint_iterate(300)
     G.solve_adjoint(H().SOURCE_MEAN, tau_adj=0.6, max_iters=300)
-    compare_adjoint(s, L, G, TOL_MEAN)
+    compare_adjoint(s, L, G, TOL if kind == O.OBJ_FFA else TOL_MEAN)
 
 
 @pytest.mark.parametrize("turb", [O.TURB_FROZEN, O.TURB_DIFFERENTIATED])

@@ -1,7 +1,11 @@
 """Precision forms against the FP64 oracle: FP32 arithmetic with FP32 storage
 and FP32 arithmetic with binary16 storage of f_i - w_i (FP16S).  Window
 accumulators, objective and gradient reductions stay FP64 in both.  The
-bounds below are the stated errors of each form on the laminar channel."""
+bounds below are the stated errors of each form, about three times the
+measured ones (the kernels are deterministic, so these do not vary from run
+to run): D2Q9 channel FP32 populations 5.3e-7, mean J 1.2e-5, gradient
+1.3e-5; FP16S 8.5e-5, 3.9e-5, 4.4e-4; D3Q19 LES box populations FP32
+4.9e-7, FP16S 2.1e-4."""
 import numpy as np
 import pytest
 
@@ -12,7 +16,9 @@ from tests.pairs import Spec, make_gpu, make_oracle, rel_err, say, state_mask
 pytestmark = pytest.mark.gpu
 
 # form: (populations after 1000 steps, mean J, gradient)
-BOUNDS = {1: (2e-6, 2e-4, 2e-3), 2: (2e-4, 2e-2, 5e-2)}
+BOUNDS = {1: (1.6e-6, 3.5e-5, 4e-5), 2: (2.5e-4, 1.2e-4, 1.3e-3)}
+# form: populations after 200 D3Q19 steps with the closure
+BOUNDS_3D = {1: 1.5e-6, 2: 6e-4}
 
 
 def channel(**kw):
@@ -68,4 +74,4 @@ def test_d3q19_precision_forms(prec):
     G.run_primal(200)
     e_f = rel_err(G.populations(), L.populations(), state_mask(s))
     print(f"d3q19 form {prec}: populations {e_f:.3e}", flush=True)
-    assert e_f < BOUNDS[prec][0] * 10
+    assert e_f < BOUNDS_3D[prec]

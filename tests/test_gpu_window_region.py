@@ -13,7 +13,8 @@ import oracle as O
 from tests.pairs import Spec, make_gpu, make_oracle, objective_tol, rel_err, say, state_mask
 
 pytestmark = pytest.mark.gpu
-TOL_MEAN = 1e-11
+TOL = 1e-12       # drag objectives: no dependence on Pi
+TOL_MEAN = 1e-11  # J_DISS and the closure read Pi (see test_gpu_parity_adjoint)
 NX, NY = 120, 41
 
 CASES = {
@@ -75,4 +76,5 @@ def test_window_mean_and_mean_flow_adjoint(name):
     e_phi = rel_err(G.adjoint(), L.adjoint(), state_mask(s))
     e_g = rel_err(G.gradient(), L.gradient())
     print(f"{name}: mean adjoint parity phi {e_phi:.3e} gradient {e_g:.3e}", flush=True)
-    assert e_phi < TOL_MEAN and e_g < TOL_MEAN
+    tol = TOL if kind in (O.OBJ_FFA, O.OBJ_MEA) else TOL_MEAN
+    assert e_phi < tol and e_g < tol
