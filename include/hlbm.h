@@ -201,6 +201,16 @@ hlbm_status hlbm_device_bytes(hlbm_lattice lat, uint64_t* bytes);
 /* Copy a porosity field d[n]; every value must be finite and in [0, 1]
  * (checked on the host for host input, on the device for device input). */
 hlbm_status hlbm_set_porosity(hlbm_lattice lat, const double* d, int64_t n, int32_t mem);
+/* The same as hlbm_set_porosity with device input, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it calls no allocating routine.  d[n] is
+ * device memory on the lattice's device.  The validation flag lives in 4
+ * bytes of a 256-byte library-owned device array, one per GPU, held until the
+ * process ends; each call clears it first.  Calls that overlap on one GPU
+ * (concurrent streams or threads) race on that flag.  Errors: INVALID (size,
+ * or a value outside [0, 1] or not finite: the field then holds the rejected
+ * values), STATE, DEVICE. */
+hlbm_status hlbm_set_porosity_noalloc(hlbm_lattice lat, const double* d, int64_t n);
 /* Build d on the device for a cylinder of diameter D centred at (xc, yc),
  * axis along z: solid fraction chi = 1 for r <= R-1, (1 + cos(pi(r-R+1)/2))/2
  * for R-1 < r < R+1, 0 beyond; d = 1 - chi (Sec. 5.1: d = 0 in the cylinder).

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,42 @@ void lat_free(hlbm_lattice_s* L, void* p) {
   if (!p) return;
   L->allocs.erase(p);
   dev_free(p);
+}
+
+// Scratch of the allocation-free entry point (hlbm_set_porosity_noalloc): a
+// library-owned device array that every GPU the library runs on holds, each
+// its own copy, until the process ends.  In host code `scratch` names a
+// host-side stand-in, not a device address: the address of a device's copy
+// is looked up once per device (with that device current, when the first
+// lattice is created on it) and only that address reaches kernels and copies.
+constexpr int kScratchInts = 64;  // 256 bytes
+__device__ __align__(256) int scratch[kScratchInts];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+hlbm_status scratch_address(int device, int** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(HLBM_E_DEVICE, "device ordinal %d out of range", device);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(HLBM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_addr[device] = (int*)p;
+  }
+  *out = g_scratch_addr[device];
+  return HLBM_OK;
+}
+
+// Clears n ints (a kernel rather than a memset: safe under stream capture).
+__global__ void k_clear_ints(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 int q_of(int stencil) { return stencil == HLBM_D2Q9 ? 9 : 19; }
@@ -370,6 +407,18 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
     return fail(HLBM_E_INVALID, "internal: plane stride %lld < %lld cells", pl, nn);
   }
   L->stream = (hipStream_t)desc->stream;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      delete L;
+      return fail(HLBM_E_DEVICE, "hipGetDevice failed");
+    }
+    L->device = dev;
+    if ((s = scratch_address(dev, &L->noalloc_scratch)) != HLBM_OK) {
+      delete L;
+      return s;
+    }
+  }
   // streaming hints for BGK primal sweeps over lattices larger than the
   // 256 MiB Infinity Cache (D2Q9 measured 160 MB slower with them, 320 MB
   // faster); which steps take them is decided per stencil at launch
@@ -450,6 +499,25 @@ hlbm_status hlbm_set_porosity(hlbm_lattice L, const double* d, int64_t n, int32_
   if (hbad) return fail(HLBM_E_INVALID, "porosity outside [0, 1] or not finite");
   L->adj_ready = 0;
   L->mea_dirty = 1;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_set_porosity_noalloc(hlbm_lattice L, const double* d, int64_t n) {
+  CHECK_LAT(L);
+  if (!d || n != L->n) return fail(HLBM_E_INVALID, "porosity needs %lld device values", (long long)L->n);
+  int* flag = L->noalloc_scratch;  // element 0 of this device's scratch array
+  if (!flag) return fail(HLBM_E_STATE, "no scratch address for the lattice's device");
+  k_clear_ints<<<1, 64, 0, L->stream>>>(flag, 1);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_set_porosity(L, d, flag);
+  if (e == hipSuccess) e = hipMemcpyAsync(L->red_host, flag, sizeof(int), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return fail(HLBM_E_DEVICE, "set_porosity_noalloc: %s", hipGetErrorString(e));
+  int bad = 0;
+  std::memcpy(&bad, L->red_host, sizeof(int));
+  L->adj_ready = 0;
+  L->mea_dirty = 1;
+  if (bad) return fail(HLBM_E_INVALID, "porosity outside [0, 1] or not finite");
   return HLBM_OK;
 }
 

@@ -99,6 +99,11 @@ struct hlbm_lattice_s {
 
   // every device buffer the handle owns, with its size (hlbm_device_bytes)
   std::unordered_map<void*, size_t> allocs;
+
+  // device the handle was created on, and the device address of that GPU's
+  // copy of the library's scratch array (the allocation-free entry point)
+  int device = 0;
+  int* noalloc_scratch = nullptr;
 };
 
 namespace hlbm {

@@ -40,7 +40,7 @@ EXPORTS = [
     "hlbm_profile_get", "hlbm_bytes_per_update", "hlbm_status_string", "hlbm_last_error",
     "hlbm_set_probe", "hlbm_get_probe", "hlbm_reconfigure", "hlbm_group_create", "hlbm_group_destroy",
     "hlbm_group_set", "hlbm_group_step", "hlbm_group_synchronize", "hlbm_run_tangent",
-    "hlbm_copy_probe", "hlbm_device_bytes",
+    "hlbm_copy_probe", "hlbm_device_bytes", "hlbm_set_porosity_noalloc",
 ]
 
 GROUP_PRIMAL, GROUP_PRIMAL_WINDOW, GROUP_ADJOINT = 0, 1, 2
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "hlbm_footprint_bytes": (i32, [P(Desc), i32, i32, i64, i32, P(C.c_uint64)]),
         "hlbm_device_bytes": (i32, [vp, P(C.c_uint64)]),
         "hlbm_set_porosity": (i32, [vp, vp, i64, i32]),
+        "hlbm_set_porosity_noalloc": (i32, [vp, vp, i64]),
         "hlbm_build_cylinder": (i32, [vp, dbl, dbl, dbl, vp, i64, i32, i32, dbl, dbl]),
         "hlbm_init_equilibrium": (i32, [vp, dbl, vp, i64, i32]),
         "hlbm_set_populations": (i32, [vp, vp, i64, i32]),
@@ -257,6 +258,17 @@ class Lattice:
         self.generation += 1
         p, n, mem, _keep = _arr_in(d, self.n)
         _check(self._lib.hlbm_set_porosity(self._h, p, n, mem))
+
+    def set_porosity_noalloc(self, d):
+        """hlbm_set_porosity_noalloc: d must be a float64 CUDA tensor on the
+        lattice's device (no staging, no allocation in the library)."""
+        self.generation += 1
+        if not (hasattr(d, "is_cuda") and d.is_cuda):
+            raise ValueError("set_porosity_noalloc takes a CUDA tensor")
+        import torch
+        if d.dtype != torch.float64 or not d.is_contiguous():
+            raise ValueError("set_porosity_noalloc takes a contiguous float64 tensor")
+        _check(self._lib.hlbm_set_porosity_noalloc(self._h, C.c_void_p(d.data_ptr()), d.numel()))
 
     def build_cylinder(self, xc, yc, D, noise=None, noise_mode=NOISE_NONE, box_half=0.0, d_solid=0.0):
         self.generation += 1
