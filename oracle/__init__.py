@@ -53,9 +53,11 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
+    # HLBM_ORACLE_LIB: another build of the same source (the sanitizer run)
+    path = os.environ.get("HLBM_ORACLE_LIB") or LIB_PATH
+    if not os.path.exists(path):
         build()
-    lib = C.CDLL(LIB_PATH)
+    lib = C.CDLL(path)
     vp = C.c_void_p
     sig = {
         "orc_create": (vp, [C.POINTER(_Params)]),

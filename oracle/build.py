@@ -13,16 +13,20 @@ SRC = os.path.join(HERE, "hlbm_oracle.c")
 LIB_PATH = os.path.join(HERE, "libhlbm_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB_PATH, sanitize: bool = False) -> str:
+    """sanitize: AddressSanitizer and UndefinedBehaviorSanitizer build (host
+    code only; any undefined behaviour aborts)."""
+    san = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
     cmd = [
-        "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", SRC, "-lm",
+        "gcc", *san, "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", out + ".tmp", SRC, "-lm",
     ]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

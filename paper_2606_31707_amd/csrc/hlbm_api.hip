@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "hlbm_host.hpp"
 #include "hlbm_internal.hpp"
 #include "hlbm_stop.hpp"
 
@@ -38,19 +39,6 @@ hlbm_status fail(hlbm_status s, const char* fmt, ...) {
   do {                                                            \
     if ((L) == nullptr) return fail(HLBM_E_INVALID, "null lattice"); \
   } while (0)
-
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
-// Plane stride in elements: a multiple of 256 B, and an odd number of 256 B
-// blocks so that the q planes do not start on the same memory channel (power-
-// of-two strides measured up to 8% slower on the D3Q19 sweeps).
-int64_t plane_stride(int64_t n, size_t ssize) {
-  if (ssize == 0 || ssize > 256) return -1;
-  const int64_t unit = 256 / (int64_t)ssize;
-  int64_t m = (n + unit - 1) / unit;
-  if (m % 2 == 0) m += 1;
-  return m * unit < round_up(n, 128) ? round_up(n, 128) : m * unit;
-}
 
 hlbm_status dev_alloc(void** p, size_t bytes) {
   if (*p) return HLBM_OK;
@@ -117,41 +105,9 @@ __global__ void k_clear_ints(int* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
-int q_of(int stencil) { return stencil == HLBM_D2Q9 ? 9 : 19; }
-int dim_of(int stencil) { return stencil == HLBM_D2Q9 ? 2 : 3; }
-size_t ssize_of(int prec) { return prec == HLBM_FP64 ? 8 : (prec == HLBM_FP32 ? 4 : 2); }
-size_t dsize_of(int prec) { return prec == HLBM_FP64 ? 8 : 4; }
-size_t asize_of(int prec) { return prec == HLBM_FP64 ? 8 : 4; }
-int nsym_of(int stencil) { return stencil == HLBM_D2Q9 ? 3 : 6; }
-int ncoef_of(int stencil) { return 3 + dim_of(stencil) + nsym_of(stencil); }
-int nb_of(int stencil) { return 1 + dim_of(stencil) + nsym_of(stencil); }
-
 hlbm_status validate_desc(const hlbm_desc* d) {
-  if (!d) return fail(HLBM_E_INVALID, "null descriptor");
-  if (d->struct_size != sizeof(hlbm_desc))
-    return fail(HLBM_E_INVALID, "hlbm_desc.struct_size %u != %zu", d->struct_size, sizeof(hlbm_desc));
-  if (d->stencil != HLBM_D2Q9 && d->stencil != HLBM_D3Q19) return fail(HLBM_E_INVALID, "bad stencil");
-  if (d->precision < HLBM_FP64 || d->precision > HLBM_FP16S) return fail(HLBM_E_INVALID, "bad precision");
-  if (d->nx < 2 || d->ny < 1 || d->nz < 1) return fail(HLBM_E_INVALID, "bad lattice size");
-  if (d->stencil == HLBM_D2Q9 && d->nz != 1) return fail(HLBM_E_INVALID, "D2Q9 needs nz = 1");
-  if ((int64_t)d->nx * d->ny * d->nz > (int64_t)1 << 31) return fail(HLBM_E_INVALID, "lattice too large");
-  if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(HLBM_E_INVALID, "tau must exceed 1/2");
-  if (!(d->smagorinsky_cs >= 0.0) || !std::isfinite(d->smagorinsky_cs))
-    return fail(HLBM_E_INVALID, "Smagorinsky constant must be >= 0");
-  if (d->bc_x < 0 || d->bc_x > 2 || d->bc_y < 0 || d->bc_y > 1 || d->bc_z < 0 || d->bc_z > 1)
-    return fail(HLBM_E_INVALID, "bad boundary kinds (only x may be INLET_OUTLET)");
-  if (d->bc_x == HLBM_BC_INLET_OUTLET) {
-    if (d->inlet_profile != HLBM_INLET_UNIFORM && d->inlet_profile != HLBM_INLET_PARABOLIC)
-      return fail(HLBM_E_INVALID, "bad inlet profile");
-    if (d->nx < 3) return fail(HLBM_E_INVALID, "inlet/outlet channel needs nx >= 3");
-  }
-  if (!std::isfinite(d->u_in)) return fail(HLBM_E_INVALID, "u_in not finite");
-  if (d->collision != HLBM_COLL_BGK && d->collision != HLBM_COLL_HRR) return fail(HLBM_E_INVALID, "bad collision");
-  if (d->cache_policy < HLBM_CACHE_AUTO || d->cache_policy > HLBM_CACHE_STREAMING)
-    return fail(HLBM_E_INVALID, "bad cache policy");
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(d->force[a])) return fail(HLBM_E_INVALID, "force not finite");
-  return HLBM_OK;
+  const char* why = desc_problem(d);
+  return why ? fail(HLBM_E_INVALID, "%s", why) : HLBM_OK;
 }
 
 // device scratch for host <-> device exchange of FP64 arrays
@@ -342,35 +298,8 @@ hlbm_status hlbm_footprint_bytes(const hlbm_desc* desc, int with_window, int wit
   hlbm_status s = validate_desc(desc);
   if (s != HLBM_OK) return s;
   if (!bytes) return fail(HLBM_E_INVALID, "null output");
-  const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
-  if (region_cells < 0 || region_cells > n) return fail(HLBM_E_INVALID, "region_cells outside [0, n]");
-  if (objective < HLBM_OBJ_FFA || objective > HLBM_OBJ_MEA) return fail(HLBM_E_INVALID, "bad objective kind");
-  const int q = q_of(desc->stencil), dim = dim_of(desc->stencil), ncoef = ncoef_of(desc->stencil);
-  const uint64_t P = (uint64_t)plane_stride(n, ssize_of(desc->precision));
-  const uint64_t G = (uint64_t)round_up((int64_t)desc->ny * desc->nz, 128);
-  const uint64_t ss = ssize_of(desc->precision), ds = dsize_of(desc->precision), as = asize_of(desc->precision);
-  const uint64_t blocks = (uint64_t)((desc->nx + BX - 1) / BX) * ((desc->ny + BY - 1) / BY) * desc->nz;
-  // populations, porosity, outlet values, reduction partials, steady-check snapshot
-  uint64_t b = P * (q * ss + ds) + G * q * ss + 8 * (2 * blocks + 8) + 8 * P * dim;
-  if (region_cells > 0) {  // objective terms and adjoint source over the region
-    const uint64_t rp = (uint64_t)round_up(region_cells, 128);
-    b += 2 * 8 * rp * ncoef;
-    if (objective == HLBM_OBJ_MEA) b += rp + 8 * q * rp;  // surface flags and source
-  }
-  if (with_window) {
-    b += P * 8 * (1 + dim);
-    if (desc->track_mean_populations) b += P * 8 * q;
-    if (desc->smagorinsky_cs > 0) b += P * 8;
-  }
-  if (with_adjoint) {
-    b += P * as * q;                                    // phi
-    b += P * as * (dim + 2 + q + nb_of(desc->stencil)); // frozen coefficients
-    b += P * 8 * (dim + 2);                             // gradient data
-    b += G * (8 * (1 + dim) + 2 * as * q);              // outlet data, outlet adjoint values
-    b += P * as * q;                                    // residual snapshot
-  }
-  *bytes = b;
-  return HLBM_OK;
+  const char* why = footprint_of(desc, with_window, with_adjoint, region_cells, objective, BX, BY, bytes);
+  return why ? fail(HLBM_E_INVALID, "%s", why) : HLBM_OK;
 }
 
 hlbm_status hlbm_device_bytes(hlbm_lattice L, uint64_t* bytes) {

@@ -15,6 +15,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhlbm.so")
+# the same sources built with 64 x 4 tiles and no XCD tile remapping (tests)
+CANARY_PATH = os.path.join(HERE, "libhlbm_canary.so")
 
 D2Q9, D3Q19 = 0, 1
 FP64, FP32, FP16S = 0, 1, 2
@@ -100,10 +102,18 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Loads libhlbm.so; raises if it is not built (no fallback exists)."""
+    """Loads libhlbm.so once per process (later calls return it); raises if it
+    is not built (no fallback exists)."""
     global _lib
     if _lib is not None:
         return _lib
+    _lib = open_library(path)
+    return _lib
+
+
+def open_library(path: str):
+    """Loads a build of the library at `path` with the call signatures set
+    (another build, e.g. the race-canary one, beside the default)."""
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
                           "python paper_2606_31707_amd/build.py")
@@ -158,7 +168,6 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
     return lib
 
 
@@ -231,8 +240,8 @@ def footprint_bytes(desc: Desc, with_window=True, with_adjoint=True, region_cell
 class Lattice:
     """One lattice on the GPU (owns an hlbm_lattice handle)."""
 
-    def __init__(self, desc: Desc | None = None, **kw):
-        self._lib = load_library()
+    def __init__(self, desc: Desc | None = None, lib=None, **kw):
+        self._lib = lib if lib is not None else load_library()
         self.desc = desc if desc is not None else make_desc(**kw)
         h = C.c_void_p()
         _check(self._lib.hlbm_create(C.byref(self.desc), C.byref(h)))

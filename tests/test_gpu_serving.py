@@ -153,3 +153,51 @@ def test_result_is_the_same_alone_and_in_the_mix():
         assert got[qid].J == alone[qid].J
         assert np.array_equal(got[qid].grad, alone[qid].grad), qid
     assert len(st.results) == len(mix) + 2
+
+
+class _RoundClock:
+    """A clock that reads the number of rounds the backend has advanced, so
+    that arrivals fall between given rounds whatever the GPU's speed."""
+
+    def __init__(self):
+        self.rounds = 0
+
+    def __call__(self):
+        return float(self.rounds)
+
+
+def _counting_server(clock):
+    b = S.GPUBackend(pack_max_cells=300_000)
+    advance = b.advance
+
+    def counted(work, n):
+        advance(work, n)
+        clock.rounds += 1
+
+    b.advance = counted
+    return S.Server(b, mem_cap_bytes=8 << 30, max_slots=16, tick=256)
+
+
+def test_query_admitted_mid_run_gives_the_same_result():
+    """Probe queries that arrive while the others are several rounds into
+    their primal, window or adjoint phases: each result is bitwise the one it
+    has alone (FP32, deterministic reductions)."""
+    say("alone vs mix, mid-run arrivals")
+    probe_small = S.Query(0, S.D2Q9, 176, 88, 1, 120.0, S.OBJ_DISS, 881)   # packed
+    probe_big = S.Query(1, S.D2Q9, 1024, 512, 1, 30.0, S.OBJ_FFA, 882)     # own launches
+    mix = [m for m in S.poisson_mix(12, rate=1e9, seed=9) if m.stencil == S.D2Q9 and m.nx <= 512][:6]
+    for i, m in enumerate(mix):
+        m.qid, m.arrival = 10 + i, 0.0
+    alone = {}
+    for pq in (probe_small, probe_big):
+        c = _RoundClock()
+        alone[pq.qid] = _counting_server(c).run([S.Query(**{**pq.__dict__, "arrival": 0.0})], clock=c).results[0]
+    probe_small.arrival, probe_big.arrival = 5.0, 9.0  # after 5 and 9 rounds of the others
+    c = _RoundClock()
+    st = _counting_server(c).run(mix + [probe_small, probe_big], clock=c)
+    got = {r.qid: r for r in st.results}
+    assert len(got) == len(mix) + 2
+    assert got[0].admitted >= 5.0 and got[1].admitted >= 9.0
+    for qid in (0, 1):
+        assert got[qid].J == alone[qid].J
+        assert np.array_equal(got[qid].grad, alone[qid].grad), qid
