@@ -716,7 +716,8 @@ def report_serving(n: int, rate: float, cap_gib: float, tick: int, slots: int):
     print(json.dumps(out), flush=True)
 
 
-def report_les(spinup: int, window: int, adj_iters: int, forms, collision: int = 0):
+def report_les(spinup: int, window: int, adj_iters: int, forms, collision: int = 0, tau_adjs=(0.0, 0.6),
+               adj_tol: float = 1e-8):
     """The 3D LES case (768 x 384 x 128 D3Q19, Smagorinsky C_S = 0.1, Re 3900,
     drag plane): FP32, FP16-shifted and FP64 population storage with FP64
     window accumulation; the mean flow of each form against the FP64 form
@@ -774,49 +775,63 @@ def report_les(spinup: int, window: int, adj_iters: int, forms, collision: int =
         means[name] = u_all
         r.update({"J_mean": J_all, "J_halves": [J_h1, J_h2], "mean_u_halves_rel_l2": l2(u_h1, u_h2),
                   "J_halves_rel": abs(J_h1 - J_h2) / abs(J_all)})
-        variants = [("fta", H.TURB_FROZEN, 0.0), ("fta_tau0.6", H.TURB_FROZEN, 0.6)]
+        def vname(kind, ta):
+            return kind if ta <= 0.0 else f"{kind}_tau{ta:g}"
+        variants = [(vname("fta", ta), H.TURB_FROZEN, ta) for ta in tau_adjs]
         if diff:
-            variants += [("diff", H.TURB_DIFFERENTIATED, 0.0), ("diff_tau0.6", H.TURB_DIFFERENTIATED, 0.6)]
+            variants += [(vname("diff", ta), H.TURB_DIFFERENTIATED, ta) for ta in tau_adjs]
         r["adjoint"] = {}
         p = G.profile()
         bpu = G.bytes_per_update()
         r["sweeps"] = {k: {"us_per_launch": p[k]["mean_us"], "GLUPS": w.n / p[k]["mean_us"] / 1e3,
                            "GB_s": bpu[k] * w.n / p[k]["mean_us"] / 1e3} for k in p if p[k]["sampled"]}
-        for vname, turb, tau_adj in variants:
+        for vn, turb, tau_adj in variants:
             ta = time.perf_counter()
             G.profile_enable(97)
-            it, rr, _ = G.solve_adjoint(H.SOURCE_MEAN, tau_adj=tau_adj, turb=turb, max_iters=adj_iters,
-                                        tol=1e-8, check_every=1000)
+            it, st, rr = 0, H.W_NOT_CONVERGED, -1.0
+            while it < adj_iters and st != H.OK:  # in blocks, each ending with a progress line
+                k, rr, st = G.solve_adjoint(H.SOURCE_MEAN, tau_adj=tau_adj, turb=turb,
+                                            max_iters=min(10000, adj_iters - it), tol=adj_tol, check_every=1000,
+                                            restart=(it == 0))
+                it += k
+                log(f"les {name} adjoint {vn}: {it} it, residual {rr:.2e}")
             g = G.gradient()
-            grads[(name, vname)] = g
+            grads[(name, vn)] = g
             pa, ba = G.profile()["adjoint"]["mean_us"], G.bytes_per_update()["adjoint"]
-            r["adjoint"][vname] = {"iters": it, "residual": rr, "seconds": time.perf_counter() - ta,
+            r["adjoint"][vn] = {"iters": it, "residual": rr, "tol": adj_tol, "converged": st == H.OK,
+                                   "seconds": time.perf_counter() - ta,
                                    "max_abs_grad": float(np.abs(g).max()), "us_per_launch": pa,
                                    "GB_s": ba * w.n / pa / 1e3 if pa > 0 else None}
-            log(f"les {name} adjoint {vname}: {it} it, residual {rr:.2e}")
+            log(f"les {name} adjoint {vn}: {it} it, residual {rr:.2e}")
         r["seconds"] = time.perf_counter() - t0
         res[name] = r
         G.close()
 
     ref = "fp64" if "fp64" in means else "fp32"
     cmp = {}
+    def vname(kind, ta):
+        return kind if ta <= 0.0 else f"{kind}_tau{ta:g}"
+    f0 = vname("fta", tau_adjs[0])
     for name in means:
         if name == ref:
             continue
         c = {"mean_u_rel_l2_vs_" + ref: l2(means[name], means[ref]),
              "J_mean_rel_vs_" + ref: abs(res[name]["J_mean"] - res[ref]["J_mean"]) / abs(res[ref]["J_mean"])}
-        if (ref, "fta") in grads and (name, "fta") in grads:
-            c["grad_fta_rel_l2_vs_" + ref] = l2(grads[(name, "fta")], grads[(ref, "fta")])
-            c["grad_fta_cosine_vs_" + ref] = cos(grads[(name, "fta")], grads[(ref, "fta")])
+        if (ref, f0) in grads and (name, f0) in grads:
+            c["grad_fta_rel_l2_vs_" + ref] = l2(grads[(name, f0)], grads[(ref, f0)])
+            c["grad_fta_cosine_vs_" + ref] = cos(grads[(name, f0)], grads[(ref, f0)])
         cmp[name] = c
-    if ("fp32", "diff") in grads:
-        g = grads
-        cmp["fp32_fta_vs_diff"] = {"cosine": cos(g[("fp32", "fta")], g[("fp32", "diff")]),
-                                   "rel_l2": l2(g[("fp32", "fta")], g[("fp32", "diff")]),
-                                   "cosine_tau0.6": cos(g[("fp32", "fta_tau0.6")], g[("fp32", "diff_tau0.6")])}
+    c2 = {}
+    for ta in tau_adjs:
+        a, b = ("fp32", vname("fta", ta)), ("fp32", vname("diff", ta))
+        if a in grads and b in grads:
+            c2[f"tau_adj {ta:g}" if ta > 0 else "tau_adj tau0"] = {"cosine": cos(grads[a], grads[b]),
+                                                                   "rel_l2": l2(grads[a], grads[b])}
+    if c2:
+        cmp["fp32_fta_vs_diff"] = c2
     out = {"report": "les", "workload": w.name, "collision": "hrr" if collision == H.COLL_HRR else "bgk",
-           "spinup_steps": spinup, "window_steps": window,
-           "adjoint_max_iters": adj_iters, "forms": res, "comparison": cmp}
+           "spinup_steps": spinup, "window_steps": window, "adjoint_max_iters": adj_iters,
+           "adjoint_tol": adj_tol, "tau_adj": list(tau_adjs), "forms": res, "comparison": cmp}
     print(json.dumps(out), flush=True)
 
 
@@ -1020,6 +1035,8 @@ def main():
     ap.add_argument("--les-adjoint", type=int, default=8000)
     ap.add_argument("--les-forms", default="fp32,fp16s,fp64")
     ap.add_argument("--les-collision", choices=["bgk", "hrr"], default="bgk")
+    ap.add_argument("--les-tau-adjs", default="0,0.6", help="adjoint relaxation times (0: tau0)")
+    ap.add_argument("--les-adjoint-tol", type=float, default=1e-8)
     ap.add_argument("--v3d-steps", type=int, default=42336)
     ap.add_argument("--v3d-adjoint", type=int, default=60000)
     ap.add_argument("--v3d-fd-scale", type=float, default=1.0 / 3.0)
@@ -1061,7 +1078,8 @@ def main():
         forms = {"fp64": H.FP64, "fp32": H.FP32, "fp16s": H.FP16S}
         report_les(args.les_spinup, args.les_window, args.les_adjoint,
                    [forms[f] for f in args.les_forms.split(",")],
-                   H.COLL_HRR if args.les_collision == "hrr" else H.COLL_BGK)
+                   H.COLL_HRR if args.les_collision == "hrr" else H.COLL_BGK,
+                   tuple(float(v) for v in args.les_tau_adjs.split(",")), args.les_adjoint_tol)
         return
     if args.report == "validation3d":
         report_validation3d(args.v3d_steps, args.v3d_adjoint, args.v3d_fd_scale, args.v3d_fd_points)
