@@ -373,7 +373,11 @@ void hlbm_group_destroy(hlbm_group g);
  * (hlbm_solve_adjoint with max_iters = 0).  Until the next hlbm_group_set the
  * members may not be advanced by any other call.  count = 0 empties it. */
 hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, const int32_t* modes, int32_t count);
-/* Advances every member by n steps / iterations (asynchronous). */
+/* Advances every member by n steps / iterations (asynchronous).  On a group
+ * with its own stream (not the null stream), a run of n >= 16 steps is
+ * launched as one HIP graph of kernel nodes, captured once and replayed while
+ * the members, their modes and n repeat (one host launch per run instead of
+ * one per kernel); otherwise, or if capture fails, one launch per step. */
 hlbm_status hlbm_group_step(hlbm_group g, int64_t n);
 hlbm_status hlbm_group_synchronize(hlbm_group g);
 

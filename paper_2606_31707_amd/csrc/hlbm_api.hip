@@ -1054,6 +1054,7 @@ extern "C" hlbm_status hlbm_group_create(void* stream, hlbm_group* out) {
 extern "C" void hlbm_group_destroy(hlbm_group g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
   dev_free(g->tab_primal);
   dev_free(g->tab_adjoint);
   dev_free(g->first_primal);
@@ -1146,18 +1147,77 @@ extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, co
   return HLBM_OK;
 }
 
+namespace {
+// The n packed launches of a step run (each step one primal and/or one
+// adjoint launch; AA parity from the step count since the last set).
+hipError_t enqueue_group_steps(hlbm_group_s* g, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    const int step = (int)((g->steps_since_set + k) & 1);
+    hipError_t e;
+    if (g->n_primal > 0 &&
+        (e = launch_primal_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_primal,
+                                  g->first_primal, g->n_primal, g->blocks_primal, step)) != hipSuccess)
+      return e;
+    if (g->n_adjoint > 0 &&
+        (e = launch_adjoint_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_adjoint,
+                                   g->first_adjoint, g->n_adjoint, g->blocks_adjoint, step)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Runs of at least this many steps on a group's own stream are launched as
+// one HIP graph: the host then enqueues one launch per run instead of one
+// per kernel (the packed kernels of small lattices take ~5 us, about as long
+// as enqueuing one launch).
+constexpr int64_t kGraphMinSteps = 16;
+
+// Captures the run into a graph unless the last one had the same launch
+// arguments, then launches it.  Returns false (nothing enqueued) if capture
+// is not possible, so that the caller launches the kernels directly.
+bool launch_group_graph(hlbm_group_s* g, int64_t n) {
+  const uint64_t key[13] = {(uint64_t)g->stencil, (uint64_t)g->precision, (uint64_t)g->collision,
+                            (uint64_t)(uintptr_t)g->tab_primal, (uint64_t)(uintptr_t)g->first_primal,
+                            (uint64_t)g->n_primal, (uint64_t)g->blocks_primal,
+                            (uint64_t)(uintptr_t)g->tab_adjoint, (uint64_t)(uintptr_t)g->first_adjoint,
+                            (uint64_t)g->n_adjoint, (uint64_t)g->blocks_adjoint, (uint64_t)n,
+                            (uint64_t)(g->steps_since_set & 1)};
+  if (!g->gexec || std::memcmp(key, g->gkey, sizeof key) != 0) {
+    if (g->gexec) {
+      (void)hipGraphExecDestroy(g->gexec);
+      g->gexec = nullptr;
+    }
+    if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    const hipError_t e = enqueue_group_steps(g, n);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(g->stream, &graph);
+    hipGraphExec_t exec = nullptr;
+    const bool ok = e == hipSuccess && e2 == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      return false;
+    }
+    g->gexec = exec;
+    std::memcpy(g->gkey, key, sizeof key);
+  }
+  return hipGraphLaunch(g->gexec, g->stream) == hipSuccess;
+}
+}  // namespace
+
 extern "C" hlbm_status hlbm_group_step(hlbm_group g, int64_t n) {
   if (!g) return fail(HLBM_E_INVALID, "null group");
   if (n < 0) return fail(HLBM_E_INVALID, "negative step count");
-  for (int64_t k = 0; k < n; ++k) {
-    const int step = (int)((g->steps_since_set + k) & 1);
-    if (g->n_primal > 0)
-      HIP_TRY(launch_primal_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_primal,
-                                   g->first_primal, g->n_primal, g->blocks_primal, step));
-    if (g->n_adjoint > 0)
-      HIP_TRY(launch_adjoint_packed(g->stream, g->stencil, g->precision, g->collision, g->tab_adjoint,
-                                    g->first_adjoint, g->n_adjoint, g->blocks_adjoint, step));
+  bool done = false;
+  if (n >= kGraphMinSteps && g->stream != nullptr && g->graph_ok) {
+    done = launch_group_graph(g, n);
+    if (!done) g->graph_ok = false;  // from now on the plain launches below
   }
+  if (!done) HIP_TRY(enqueue_group_steps(g, n));
   for (int i = 0; i < g->count; ++i) {
     hlbm_lattice_s* L = g->members[i];
     if (g->modes[i] == HLBM_GROUP_ADJOINT) {

@@ -189,6 +189,11 @@ struct hlbm_group_s {
   int* first_adjoint = nullptr;
   size_t cap_primal = 0, cap_adjoint = 0;  // members the device tables hold
   int64_t steps_since_set = 0;
+  // the last multi-step run of packed launches, captured as a HIP graph
+  // (kernel nodes only) and replayed while the launch arguments repeat
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gkey[13] = {};  // launch arguments the graph was captured with
+  bool graph_ok = true;    // false after a failed capture: plain launches
   hlbm_lattice_s** members = nullptr;
   int32_t* modes = nullptr;
   int count = 0;

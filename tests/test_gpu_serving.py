@@ -201,3 +201,46 @@ def test_query_admitted_mid_run_gives_the_same_result():
     for qid in (0, 1):
         assert got[qid].J == alone[qid].J
         assert np.array_equal(got[qid].grad, alone[qid].grad), qid
+
+
+def test_group_graph_replays_match_individual_launches():
+    """On a stream of its own a group launches each 256-step run as one HIP
+    graph, captured once and replayed while the members repeat.  Every replay
+    (with the program's own eager work and synchronisations between them) and
+    every recapture (new modes) gives bitwise the results of the members
+    advanced one by one with their own launches."""
+    import torch
+    from paper_2606_31707_amd import hlbm as H
+    say("group graph replays")
+    stream = torch.cuda.Stream()
+    grp = H.Group(stream=stream.cuda_stream)
+    shapes = [(96, 48, 1), (128, 64, 2), (144, 72, 3)]
+    packed = [_lat(H, nx, ny, 1, seed=sd, stream=stream.cuda_stream) for nx, ny, sd in shapes]
+    solo = [_lat(H, nx, ny, 1, seed=sd) for nx, ny, sd in shapes]
+    for rnd in range(4):  # the first run captures, the next three replay
+        grp.set(packed, [H.GROUP_PRIMAL] * 3)
+        grp.step(256)
+        grp.synchronize()
+        for a in solo:
+            a.run_primal(256)
+        for a, b in zip(solo, packed):
+            assert np.array_equal(a.populations(), b.populations()), rnd
+    for rnd in range(2):  # new modes: a new capture, then a replay
+        grp.set(packed, [H.GROUP_PRIMAL_WINDOW] * 3)
+        grp.step(128)
+        grp.synchronize()
+        for a in solo:
+            a.run_primal(128, accumulate=True)
+        for a, b in zip(solo, packed):
+            assert np.array_equal(a.field(H.FIELD_MEAN_U), b.field(H.FIELD_MEAN_U)), rnd
+    for lat in solo + packed:
+        lat.solve_adjoint(H.SOURCE_MEAN, tau_adj=0.6, turb=H.TURB_FROZEN, max_iters=0)
+    for rnd in range(3):
+        grp.set(packed, [H.GROUP_ADJOINT] * 3)
+        grp.step(64)
+        grp.synchronize()
+        for a in solo:
+            a.solve_adjoint(H.SOURCE_MEAN, tau_adj=0.6, turb=H.TURB_FROZEN, max_iters=64, restart=False)
+        for a, b in zip(solo, packed):
+            assert np.array_equal(a.gradient(), b.gradient()), rnd
+    grp.close()
