@@ -126,6 +126,9 @@ struct Geo {
   int64_t gplane;  // outlet (y, z) plane stride (elements)
   int inlet_profile;
   double u_in;
+  // Whether the odd step's 32-bit lane offsets hold every slot offset of a
+  // tile, (3 nx + 256) * 8 < 2^32 bytes (the fast-lane slot addressing).
+  int slot32;
 };
 
 __device__ __forceinline__ int64_t cell_of(const Geo& g, int x, int y, int z) {

@@ -116,6 +116,71 @@ __device__ __forceinline__ uint32_t lane_offset(uint32_t v) {
   return v;
 }
 
+// Slot addressing of the odd AA step on its fast lanes (cells whose
+// neighbours are lattice cells, or the inlet/outlet ends).  The odd step
+// reads direction opp(p) from, and writes direction p to, the same slot:
+// plane p at cell c + xi_p.  Its byte address is split three ways:
+//  * a scalar base per plane, A + p plane + c0 - nx + cz_p nx ny, reached by
+//    stepping one plane stride at a time (plus the z shift), so that no
+//    64-bit multiplication is spent on it (with the offsets formed from
+//    plane, nx and ny at each access, the D3Q19 FP16S odd step issued about
+//    600 scalar instructions per wavefront, 3.5 times the even step);
+//  * a 32-bit lane offset per y shift, lo + (cy_p + 1) nx, three per cell;
+//  * the x shift cx_p as the instruction's immediate offset.
+// The lane offsets stay below 2^32 bytes where Geo::slot32 holds (checked on
+// the host); elsewhere the odd step takes its generic path.
+template <int Q, typename S>
+struct OddSlots {
+  typedef typename Glob<char>::type gchar;
+  uint64_t plane0;  // scalar base of plane 0, bytes
+  uint64_t pstep;   // plane stride, bytes
+  uint64_t zstep;   // xy-layer stride, bytes
+  uint32_t v[3];    // lane offsets for cy = -1, 0, +1, bytes
+  __device__ __forceinline__ OddSlots(const Geo& g, const void* A, int64_t c0, uint32_t lo) {
+    // (wave_uniform64 combines the two halves as unsigned words: the builtin
+    // returns int, which a plain | would sign-extend into the high word)
+    plane0 = (uint64_t)wave_uniform64((int64_t)((uint64_t)A + (uint64_t)((c0 - g.nx) * (int64_t)sizeof(S))));
+    pstep = (uint64_t)wave_uniform64(g.plane * (int64_t)sizeof(S));
+    zstep = (uint64_t)wave_uniform64((int64_t)g.nx * g.ny * (int64_t)sizeof(S));
+    const uint32_t nxb = (uint32_t)g.nx * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      v[j] = lo * (uint32_t)sizeof(S) + (uint32_t)j * nxb;
+      asm("" : "+v"(v[j]));  // kept as a 32-bit lane offset
+    }
+  }
+  // The next plane's base from this one's (kept in scalar registers).
+  __device__ __forceinline__ uint64_t next(uint64_t pb) const {
+    pb += pstep;
+    asm("" : "+s"(pb));
+    return pb;
+  }
+  // Slot of plane p, given plane p's base.
+  __device__ __forceinline__ typename Glob<S>::type* slot(uint64_t pb, int p) const {
+    using L = Lat<Q>;
+    if (L::cz[p] > 0) pb += zstep;
+    if (L::cz[p] < 0) pb -= zstep;
+    return (typename Glob<S>::type*)((gchar*)pb + v[L::cy[p] + 1] + L::cx[p] * (int)sizeof(S));
+  }
+};
+
+// Reach of the fast lanes (OddSlots): an outlet lane's slots of planes
+// with cx = +1 lie at cell indices up to n (one past the plane's cells, for
+// cy = +1 and, in 3D, cz = +1), an inlet lane's slots of planes with cx = -1
+// down to -1.  Both stay inside the population array when no plane of the
+// first kind is the last one and no plane of the second kind is the first
+// (the rest direction).
+template <int Q>
+constexpr bool odd_reach_in_bounds() {
+  using L = Lat<Q>;
+  for (int p = 0; p < Q; ++p) {
+    if (L::cx[p] == 1 && L::cy[p] == 1 && (L::D == 2 || L::cz[p] == 1) && p == Q - 1) return false;
+    if (L::cx[p] == -1 && p == 0) return false;
+  }
+  return true;
+}
+static_assert(odd_reach_in_bounds<9>() && odd_reach_in_bounds<19>(), "odd-step fast lanes would leave the array");
+
 // Signed sum of the components selected by the (compile-time) lattice
 // coefficients a, b, c in {-1, 0, 1}; zero terms are never formed, so no
 // floating-point operation is spent on them.
@@ -631,7 +696,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   bool fast = true;
   if constexpr (ODD) {
     const bool rows = y > 0 && y < g.ny - 1 && (L::D == 2 || (z > 0 && z < g.nz - 1));
-    fast = rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
+    fast = g.slot32 && rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
   }
   T s[Q];
   if (inlet && !fast) {  // odd step, inlet cell of a wall row: pinned, pushed
@@ -659,7 +724,30 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = (T)ld_stream<NT>(&at(A, k * g.plane + c0, lo));
     __builtin_amdgcn_sched_barrier(0);
+  } else if (fast && ACC == 0) {
+    // Every fast lane requests all its slots, the inlet and outlet lanes
+    // included: their requests across the row end (x - xi_k = -1 or nx) land
+    // on in-bounds slots of other cells (OddSlots, odd_reach_in_bounds), and
+    // those values are replaced below.
+    const OddSlots<Q, S> sl(g, A, c0, lo);
+    uint64_t pb = sl.plane0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      s[L::opp[p]] = (T)ld_stream<NT>(sl.slot(pb, p));
+      pb = sl.next(pb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (outlet) {  // upstream (nx, y - cy, z - cz): the virtual column
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (L::cx[k] == -1) s[k] = (T)ghost[k * g.gplane + (y - L::cy[k]) + (int64_t)g.ny * (z - L::cz[k])];
+    }
   } else if (fast) {
+    // The window steps address each slot from its own scalar base (plane and
+    // neighbour offset formed per access): with the plane-stepped bases of
+    // OddSlots the D2Q9 window steps measured 3-7 % slower (same addresses;
+    // the plain steps, which are not bound by memory alone in FP16, 7-15 %
+    // faster with them).
     if (!inlet) {  // the inlet's upstream lies outside the lattice
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -793,10 +881,19 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       }
     }
   } else {
-    if (fast) {
+    if (fast && ACC == 0) {
+      const OddSlots<Q, S> sl(g, A, c0, lo);
+      uint64_t pb = sl.plane0;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        // populations leaving through the inlet or outlet end are dropped
+        if (!((L::cx[p] == -1 && inlet) || (L::cx[p] == 1 && outlet)))
+          st_stream<NT>(sl.slot(pb, p), to_store<S>(s[p]));
+        pb = sl.next(pb);
+      }
+    } else if (fast) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        // populations leaving through the inlet or outlet end are dropped
         if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
         st_stream<NT>(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), to_store<S>(s[k]));
       }
@@ -880,15 +977,19 @@ template <int Q, typename S, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_copy_probe(const Geo g, S* __restrict__ A,
                                                     const typename Prec<S>::Dd* __restrict__ dpor,
                                                     int* __restrict__ sink) {
-  using L = Lat<Q>;
   SWEEP_PROLOGUE_RUNS
   if (!valid) return;
   const auto d = at(dpor, tile_c0, tile_lo);
   S v[Q];
-  const bool nb = ODD && interior_cell<Q>(g, x, y, z);
-  if (nb) {
+  const bool nb = ODD && g.slot32 && interior_cell<Q>(g, x, y, z);
+  if (nb) {  // the slots of plane p at c + xi_p, addressed as the odd sweep does
+    const OddSlots<Q, S> sl(g, A, tile_c0, tile_lo);
+    uint64_t pb = sl.plane0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) v[k] = ld_stream<NT>(&at(A, L::opp[k] * g.plane + tile_c0 - nb_offset<Q>(g, k), tile_lo));
+    for (int p = 0; p < Q; ++p) {
+      v[p] = ld_stream<NT>(sl.slot(pb, p));
+      pb = sl.next(pb);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) v[k] = ld_stream<NT>(&at(A, k * g.plane + tile_c0, tile_lo));
@@ -900,8 +1001,13 @@ __global__ __launch_bounds__(256) void k_copy_probe(const Geo g, S* __restrict__
   for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(v[k]));
   if (d < 0) *sink = 1;  // never taken (d is in [0, 1]); keeps the porosity load
   if (nb) {
+    const OddSlots<Q, S> sl(g, A, tile_c0, tile_lo);
+    uint64_t pb = sl.plane0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, L::opp[k] * g.plane + tile_c0 - nb_offset<Q>(g, k), tile_lo), v[k]);
+    for (int p = 0; p < Q; ++p) {
+      st_stream<NT>(sl.slot(pb, p), v[p]);
+      pb = sl.next(pb);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) st_stream<NT>(&at(A, k * g.plane + tile_c0, tile_lo), v[k]);
@@ -1919,7 +2025,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   bool fast = true;
   if constexpr (ODD) {
     const bool rows = y > 0 && y < g.ny - 1 && (D == 2 || (z > 0 && z < g.nz - 1));
-    fast = rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
+    fast = g.slot32 && rows && ((x > 0 && x < g.nx - 1) || inlet || outlet);
   }
   if (inlet && !fast) {  // odd step, inlet cell of a wall row
 #pragma unroll
@@ -1947,16 +2053,21 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
     __builtin_amdgcn_sched_barrier(0);
     if (outlet) adjoint_zero_outlet<Q, SA>(g, x, y, z, ph);
   } else if (fast) {
-    if (!inlet) {  // the inlet's upstream lies outside the lattice
+    // as in the primal sweep: every fast lane requests all its slots; the
+    // inlet's values are replaced below, the outlet's from beyond x = nx-1 here
+    const OddSlots<Q, SA> sl(g, A, c0, lo);
+    uint64_t pb = sl.plane0;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        if (L::cx[k] == -1 && outlet)
-          ph[k] = (T)0;
-        else
-          ph[k] = ld_stream(&at(A, L::opp[k] * g.plane + c0 - nb_offset<Q>(g, k), lo));
-      }
+    for (int p = 0; p < Q; ++p) {
+      ph[L::opp[p]] = ld_stream(sl.slot(pb, p));
+      pb = sl.next(pb);
     }
     __builtin_amdgcn_sched_barrier(0);
+    if (outlet) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (L::cx[k] == -1) ph[k] = (T)0;
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {  // beyond the outlet: no adjoint inflow
@@ -2106,11 +2217,13 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
 #pragma unroll
     for (int i = 0; i < Q; ++i) st_stream<NT>(&at(A, i * g.plane + c0, lo), lam[i]);
   } else if (fast) {
+    const OddSlots<Q, SA> sl(g, A, c0, lo);
+    uint64_t pb = sl.plane0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
+    for (int p = 0; p < Q; ++p) {
       // values leaving through the inlet or outlet end are dropped
-      if ((L::cx[k] == -1 && inlet) || (L::cx[k] == 1 && outlet)) continue;
-      st_stream(&at(A, k * g.plane + c0 + nb_offset<Q>(g, k), lo), lam[L::opp[k]]);
+      if (!((L::cx[p] == -1 && inlet) || (L::cx[p] == 1 && outlet))) st_stream(sl.slot(pb, p), lam[L::opp[p]]);
+      pb = sl.next(pb);
     }
   } else {
 #pragma unroll

@@ -19,6 +19,7 @@ Geo make_geo(const hlbm_lattice_s* L) {
   g.gplane = L->gplane;
   g.inlet_profile = L->desc.inlet_profile;
   g.u_in = L->desc.u_in;
+  g.slot32 = (3 * (int64_t)g.nx + 256) * 8 < ((int64_t)1 << 32);
   return g;
 }
 
