@@ -254,16 +254,15 @@ __device__ __forceinline__ void cell_moments(const T (&s)[Q], T& drho, T& jx, T&
   }
 }
 
-// Non-equilibrium momentum flux with respect to f^eq(rho, u) from shifted
-// populations: Pi_ab = sum xi_a xi_b s - (drho/3) delta_ab - j_a j_b / rho.
-// Order: xx, yy, zz, xy, xz, yz (zz, xz, yz zero in 2D).
+// Second moments p_ab = sum xi_a xi_b s of the shifted populations, in the
+// order xx, yy, zz, xy, xz, yz (zz, xz, yz zero in 2D).
 template <int Q, typename T>
-__device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T jz, T ir,
-                                         T (&P)[6]) {
+__device__ __forceinline__ void second_moments(const T (&s)[Q], T (&p)[6]) {
   using L = Lat<Q>;
   // Signed sums over the directions with a nonzero coefficient, each started
   // from its first term (no 0 + v), in direction order.
-  T p[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < 6; ++m) p[m] = (T)0;
   bool h[6] = {false, false, false, false, false, false};
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
@@ -276,6 +275,12 @@ __device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T 
       h[m] = true;
     }
   }
+}
+
+// Non-equilibrium momentum flux with respect to f^eq(rho, u) from the second
+// moments: Pi_ab = p_ab - (drho/3) delta_ab - j_a j_b / rho (same order).
+template <int Q, typename T>
+__device__ __forceinline__ void neq_from_moments(const T (&p)[6], T drho, T jx, T jy, T jz, T ir, T (&P)[6]) {
   const T pxx = p[0], pyy = p[1], pzz = p[2], pxy = p[3], pxz = p[4], pyz = p[5];
   const T d3 = drho / (T)3;
   P[0] = pxx - d3 - jx * jx * ir;
@@ -290,6 +295,14 @@ __device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T 
     P[4] = 0;
     P[5] = 0;
   }
+}
+
+// The same from the shifted populations.
+template <int Q, typename T>
+__device__ __forceinline__ void neq_flux(const T (&s)[Q], T drho, T jx, T jy, T jz, T ir, T (&P)[6]) {
+  T p[6];
+  second_moments<Q, T>(s, p);
+  neq_from_moments<Q, T>(p, drho, jx, jy, jz, ir, P);
 }
 
 template <typename T>
@@ -531,32 +544,25 @@ __device__ __forceinline__ void inlet_state(const Geo& g, int y, T (&s)[Q]) {
 // equilibrium at (rho, u~ = d u), f^(1) the regularized non-equilibrium part
 // with Hermite coefficients a1 = (1 - d) j, a2 = sum xi xi s - drho/3 I -
 // rho u~u~ (projection) and a3 recursive (a3_aab = 2 u~_a a2_ab + u~_b a2_aa)
-// on the supported third-order components.
+// on the supported third-order components.  The caller passes ir = 1/rho and
+// the second moments p = sum xi xi s (second_moments), which the closure
+// shares.
 template <int Q, typename T>
-__device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz, T d, T omega,
-                                            const double* force) {
+__device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz, T ir, T d, T omega,
+                                            const double* force, const T (&p)[6]) {
   using L = Lat<Q>;
   using H = H3Types<Q>;
   constexpr int D = L::D;
-  const T rho = (T)1 + drho, ir = (T)1 / rho;
-  const T j[3] = {jx, jy, jz};
+  const T rho = (T)1 + drho;
   const T ut[3] = {d * jx * ir, d * jy * ir, d * jz * ir};
-  T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-  for (int k = 0; k < Q; ++k)
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = a; b < D; ++b)
-        if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) S[a][b] += (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * s[k];
+  // S = sum xi xi s from the caller's second moments p (xx, yy, zz, xy, xz, yz)
+  const int pm[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
   T a2[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      a2[a][b] = (a < D && b < D) ? S[lo][hi] - (a == b ? drho / (T)3 : (T)0) - rho * ut[a] * ut[b] : (T)0;
-    }
+    for (int b = 0; b < 3; ++b)
+      a2[a][b] = (a < D && b < D) ? p[pm[a][b]] - (a == b ? drho / (T)3 : (T)0) - rho * ut[a] * ut[b] : (T)0;
   const T tt = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
   const T tr = a2[0][0] + a2[1][1] + a2[2][2];
   T e3c[H::N], a3[H::N];
@@ -566,32 +572,47 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
     e3c[t] = rho * ut[a] * ut[a] * ut[b];
     a3[t] = (T)2 * ut[a] * a2[a][b] + ut[b] * a2[a][a];
   }
+  // Per opposite pair (k, opp k): xi.u~, xi.j and the third-order terms
+  // change sign, the second-order terms do not, so each pair is one
+  // symmetric part plus or minus one antisymmetric part; only the nonzero
+  // lattice coefficients enter the sums.
   const T omd = (T)1 - d, om1 = (T)1 - omega;
+  const T base = drho - (T)1.5 * rho * tt;  // the equilibrium's isotropic part
+  const T ntr = -tr / (T)3;                  // the isotropic part of xi xi : a2
+  const T rho3 = (T)3 * rho, rho45 = (T)4.5 * rho, omd3 = (T)3 * omd;
+  s[0] = (T)L::w[0] * base + om1 * ((T)L::w[0] * (T)4.5 * ntr);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    T cu = 0, cj = 0, n2 = -tr / (T)3, e3 = 0, n3 = 0;
+  for (int k = 1; k < Q; ++k) {
+    if (L::opp[k] < k) continue;
+    const int o = L::opp[k];
+    const T cu = csum<T>(L::cx[k], L::cy[k], L::cz[k], ut[0], ut[1], ut[2]);
+    const T cj = csum<T>(L::cx[k], L::cy[k], L::cz[k], jx, jy, jz);
+    T n2 = ntr, e3 = 0, n3 = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      cu += (T)lat_c<Q>(k, a) * ut[a];
-      cj += (T)lat_c<Q>(k, a) * j[a];
+    for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = 0; b < D; ++b)
         if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) n2 += (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * a2[a][b];
-    }
+    bool first = true;
 #pragma unroll
     for (int t = 0; t < H::N; ++t) {
       const T h = (T)h3<Q>(k, t);
       if (h != (T)0) {
-        e3 += h * e3c[t];
-        n3 += h * a3[t];
+        e3 = first ? h * e3c[t] : e3 + h * e3c[t];
+        n3 = first ? h * a3[t] : n3 + h * a3[t];
+        first = false;
       }
     }
     const T w = (T)L::w[k];
-    const T feqs = w * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * tt) + (T)13.5 * e3);
-    const T f1 = w * ((T)3 * omd * cj + (T)4.5 * n2 + (T)13.5 * n3);
-    const T fk = (T)(3.0 * L::w[k]) * ((T)L::cx[k] * (T)force[0] + (T)L::cy[k] * (T)force[1] +
-                                        (T)L::cz[k] * (T)force[2]);
-    s[k] = feqs + om1 * f1 + fk;
+    const T sym = w * (base + rho45 * cu * cu) + om1 * (w * (T)4.5 * n2);
+    const T asy = w * (rho3 * cu + (T)13.5 * e3) + om1 * (w * (omd3 * cj + (T)13.5 * n3));
+    s[k] = sym + asy;
+    s[o] = sym - asy;
+  }
+  if (force[0] != 0.0 || force[1] != 0.0 || force[2] != 0.0) {  // body force 3 w xi.F
+#pragma unroll
+    for (int k = 1; k < Q; ++k)
+      s[k] += (T)(3.0 * L::w[k]) * csum<T>(L::cx[k], L::cy[k], L::cz[k], (T)force[0], (T)force[1], (T)force[2]);
   }
 }
 
@@ -775,9 +796,14 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   if (cell == c.probe_cell && !inlet) *c.probe_out = (double)(jy * ir);
   T omega = (T)c.omega0;
   T taue = (T)c.tau0;
+  T p2[6];  // second moments, shared by the closure and the HRR collision
+  if constexpr (HRR) second_moments<Q, T>(s, p2);
   if (c.smag) {
     T P[6];
-    neq_flux<Q, T>(s, drho, jx, jy, jz, ir, P);
+    if constexpr (HRR)
+      neq_from_moments<Q, T>(p2, drho, jx, jy, jz, ir, P);
+    else
+      neq_flux<Q, T>(s, drho, jx, jy, jz, ir, P);
     const T tau0 = (T)c.tau0;
     taue = (T)0.5 * (tau0 + sqrt(tau0 * tau0 + (T)c.kS * sqrt(frob2(P))));
     omega = (T)1 / taue;
@@ -831,7 +857,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
 
   if constexpr (HRR) {
-    hrr_collide<Q, T>(s, drho, jx, jy, jz, d, omega, c.force);
+    hrr_collide<Q, T>(s, drho, jx, jy, jz, ir, d, omega, c.force, p2);
   } else {
     // s <- (1 - omega) s + omega (f^eq(rho, u~) - w), u~ = d j / rho, written
     // per opposite pair (k, opp k): with cu = xi_k . u~ the equilibrium is
