@@ -1235,11 +1235,16 @@ __global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox
                                                        const typename Prec<S>::Dd* __restrict__ dpor,
                                                        double* __restrict__ acc_obj) {
   using T = typename Prec<S>::T;
-  const int x = ob.lo[0] + blockIdx.x * BX + threadIdx.x;
-  const int y = ob.lo[1] + blockIdx.y * BY + threadIdx.y;
-  const int z = ob.lo[2] + blockIdx.z;
+  // One lane per region cell, in region order (a 1-cell-thick drag plane
+  // fills every lane; a 2D grid of lattice tiles over it left one lane in 128
+  // active).
+  const uint32_t rn0 = (uint32_t)ob.rn[0], rn1 = (uint32_t)ob.rn[1];
+  const uint32_t ri = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!ob.active || ri >= rn0 * rn1 * (uint32_t)ob.rn[2]) return;
+  const uint32_t q = ri / rn0;
+  const int x = ob.lo[0] + (int)(ri - q * rn0), y = ob.lo[1] + (int)(q % rn1), z = ob.lo[2] + (int)(q / rn1);
   int64_t r;
-  if (x >= g.nx || y >= g.ny || !region_index<Q>(ob, x, y, z, r)) return;
+  if (x >= g.nx || y >= g.ny || z >= g.nz || !region_index<Q>(ob, x, y, z, r)) return;
   const int64_t cell = cell_of(g, x, y, z);
   T s[Q];
   load_state<Q, S, T>(g, A, ghost, parity, x, y, z, cell, s);

@@ -123,13 +123,13 @@ static void primal_mode(hlbm_lattice_s* L, int accumulate) {
   const int64_t rcells = (int64_t)L->rn[0] * L->rn[1] * L->rn[2];
   if (L->obj_set && rcells * 8 <= L->n) {
     using Dd = typename Prec<S>::Dd;
-    const dim3 rg((L->rn[0] + BX - 1) / BX, (L->rn[1] + BY - 1) / BY, L->rn[2]);
+    const dim3 rg((unsigned)((rcells + 255) / 256));  // one lane per region cell
     if (mea)
-      k_window_region<Q, S, true><<<rg, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+      k_window_region<Q, S, true><<<rg, 256, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
                                                                 (const S*)L->ghost, L->parity,
                                                                 (const Dd*)L->dpor, L->acc_obj);
     else
-      k_window_region<Q, S, false><<<rg, kBlock, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
+      k_window_region<Q, S, false><<<rg, 256, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
                                                                  (const S*)L->ghost, L->parity,
                                                                  (const Dd*)L->dpor, L->acc_obj);
     primal_variant<Q, S, 3, HRR>(L);
