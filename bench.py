@@ -1021,6 +1021,9 @@ def main():
     ap.add_argument("--cpu-primal", type=int, default=40)
     ap.add_argument("--cpu-adjoint", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="leave out the short serving stream")
+    ap.add_argument("--serving-queries", type=int, default=64,
+                    help="queries of the serving stream the benchmark line reports beside the headline")
     ap.add_argument("--report", choices=["differentiation", "serving", "les", "validation3d", "tangent", "oracle",
                                          "sweeps"],
                     default=None,
@@ -1210,9 +1213,28 @@ def bench_les(args):
     if not args.no_vortex:
         out["vortex_re100_1100x410"] = vortex_extra(args)
     q.G.close()
+    if not args.no_serving:
+        out["serving"] = serving_extra(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_les(w, args.cpu_les_spinup, args.cpu_les_window)
     return out
+
+
+def serving_extra(args):
+    """Latency under load beside the headline: a short Poisson stream of the
+    serving mix (continuous batching, packed small lattices), p50/p99."""
+    from paper_2606_31707_amd import serving as S
+    n, rate = args.serving_queries, args.rate
+    srv = S.Server(S.GPUBackend(), mem_cap_bytes=int(args.mem_cap_gib * (1 << 30)), max_slots=args.slots,
+                   tick=args.tick)
+    st = srv.run(S.poisson_mix(n, rate)).summary()
+    log(f"serving: {st['completed']}/{n} queries, p50 {st['p50_latency_s']:.2f} s, "
+        f"p99 {st['p99_latency_s']:.2f} s, {st['aggregate_MLUPS']:.0f} MLUPS")
+    return {"queries": n, "rate_qps": rate, "precision": "fp32", "mem_cap_GiB": args.mem_cap_gib,
+            "mix": "70 % D2Q9 128x64..512x256, 25 % D2Q9 1024x512, 5 % D3Q19 192x96x64; Re 20..200; "
+                   "drag or dissipation; Poisson arrivals (seed 2026)",
+            **st,
+            "note": "wall-clock latency from arrival to gradient; a longer stream: --report serving"}
 
 
 def vortex_extra(args):
