@@ -441,7 +441,7 @@ def kernel_kind(name: str):
         if it is None:
             return None, None
         base, targs = it
-    if base in ("k_primal", "k_primal_stream"):
+    if base in ("k_primal", "k_primal_stream", "k_primal_wstream"):
         return ("primal" if targs[3] == "0" else "primal_window"), targs[2]
     if base == "k_window_region":
         return "region", None
@@ -1165,7 +1165,7 @@ def bench_les(args):
                      "GB_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "launches_timed": prof[k]["sampled"]}
     dom = max(sweeps, key=lambda k: sweeps[k]["ms_per_step"])
     names = {"primal": "k_primal<19, float, *, 0, false> (AA step, Smagorinsky, no window)",
-             "primal_window": "k_window_region<19, float, false> + k_primal<19, float, *, 3, false> "
+             "primal_window": "k_window_region<19, float, false> + k_primal(_stream|_wstream)<19, float, *, 3, false> "
                               "(AA step with the FP64 window: rho, j, tau_eff sums; drag-plane terms by the "
                               "region pass)",
              "adjoint": "k_adjoint<19, float, *, false, false> (mean-flow adjoint sweep, frozen turbulence)"}

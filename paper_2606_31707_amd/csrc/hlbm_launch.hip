@@ -92,7 +92,7 @@ static void primal_variant(hlbm_lattice_s* L) {
   // Streaming hints (lattices above the Infinity Cache): both D2Q9 steps;
   // only the D3Q19 even step, whose accesses are the cell's own slots (the
   // odd step's z neighbours reuse lines one xy layer later and ran 7 %
-  // slower with the hints).
+  // slower with the hints); the D3Q19 odd window step on its window sums.
   if (L->stream_nt) {
     if (L->parity == 0) {
       k_primal_stream<Q, S, false, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
@@ -100,6 +100,10 @@ static void primal_variant(hlbm_lattice_s* L) {
     }
     if constexpr (Q == 9) {
       k_primal_stream<Q, S, true, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
+      return;
+    }
+    if constexpr (ACC != 0) {  // D3Q19 odd window step: streaming hints on the window sums only
+      k_primal_wstream<Q, S, true, ACC, HRR><<<grid, block, 0, L->stream>>>(g, c, ob, A, dp, gh, acc);
       return;
     }
   }

@@ -23,6 +23,7 @@ def test_kernel_names_map_to_sweep_kinds():
         "void hlbm::k_primal_stream<9, double, false, 0, false>(hlbm::Geo)": ("primal", "false"),
         "_ZN4hlbm8k_primalILi19EDF16_Lb1ELi0ELb0EEEvNS_3GeoENS_4CollE": ("primal", "true"),
         "_ZN4hlbm15k_primal_streamILi9EDF16_Lb0ELi3ELb1EEEvNS_3GeoE": ("primal_window", "false"),
+        "void hlbm::k_primal_wstream<19, float, true, 3, false>(hlbm::Geo)": ("primal_window", "true"),
         "void hlbm::k_adjoint<19, float, true, false, false>(hlbm::Geo)": ("adjoint", "true"),
         "void hlbm::k_adjoint_stream<9, double, false, false>(hlbm::Geo)": ("adjoint", "false"),
         "void hlbm::k_window_region<19, float, false>(hlbm::Geo)": ("region", None),
