@@ -449,6 +449,8 @@ def kernel_kind(name: str):
         return "adjoint", targs[2]
     if base == "k_adjoint_stream":
         return "adjoint", "false"
+    if base == "k_adjoint_pstream":
+        return "adjoint", "true"
     if base == "k_copy_probe":
         odd, nt = targs[2] == "true", targs[3] == "true"
         return ("copy_odd" if odd else "copy_own") + ("_nt" if nt else ""), None

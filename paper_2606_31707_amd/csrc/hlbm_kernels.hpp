@@ -2050,7 +2050,7 @@ __device__ __forceinline__ double hrr_dphi_dd(const double (&ph)[Q], const doubl
   return dA + (1.0 - omega) * dB;
 }
 
-template <int Q, typename SA, bool ODD, bool HRR, bool MEA, bool NT = false>
+template <int Q, typename SA, bool ODD, bool HRR, bool MEA, bool NT = false, bool NTP = NT>
 __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, const AdjC& ac, SA* __restrict__ A,
                                              const SA* __restrict__ prep, const double* __restrict__ src,
                                              const double* __restrict__ oprep, const SA* __restrict__ pv_in,
@@ -2081,13 +2081,13 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   // issued after them would start a second memory round trip.
   T tx = (T)0, ty = (T)0, tz = (T)0, d = (T)0, omega = (T)0;
   if constexpr (!HRR) {
-    tx = at(prep, c0, lo);
-    ty = at(prep, g.plane + c0, lo);
-    if constexpr (D == 3) tz = at(prep, 2 * g.plane + c0, lo);
-    d = at(prep, D * g.plane + c0, lo);
+    tx = ld_stream<NTP>(&at(prep, c0, lo));
+    ty = ld_stream<NTP>(&at(prep, g.plane + c0, lo));
+    if constexpr (D == 3) tz = ld_stream<NTP>(&at(prep, 2 * g.plane + c0, lo));
+    d = ld_stream<NTP>(&at(prep, D * g.plane + c0, lo));
     // per-cell omega (LES): plane D + 1; otherwise the load repeats d's
     // (no branch between the loads) and the constant is taken
-    const T om = at(prep, (ac.les ? D + 1 : D) * g.plane + c0, lo);
+    const T om = ld_stream<NTP>(&at(prep, (ac.les ? D + 1 : D) * g.plane + c0, lo));
     omega = ac.les ? om : (T)ac.omega0;
   }
   T ph[Q];  // phihat_k = phi_opp(k)
@@ -2195,12 +2195,12 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
       lam[o] = omc * ph[k] + (oPhr - e);
     }
     if (ac.diff) {  // differentiated Smagorinsky: (sum_j phi_j f^neq_j) (1/tau^2) dtau/df_i
-      T sd = ph[0] * (T)at(prep, (D + 2 + L::opp[0]) * g.plane + c0, lo);
+      T sd = ph[0] * (T)ld_stream<NTP>(&at(prep, (D + 2 + L::opp[0]) * g.plane + c0, lo));
 #pragma unroll
-      for (int k = 1; k < Q; ++k) sd += ph[k] * (T)at(prep, (D + 2 + L::opp[k]) * g.plane + c0, lo);
+      for (int k = 1; k < Q; ++k) sd += ph[k] * (T)ld_stream<NTP>(&at(prep, (D + 2 + L::opp[k]) * g.plane + c0, lo));
       T b[Coef<Q>::NB];
 #pragma unroll
-      for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = at(prep, (D + 2 + Q + m) * g.plane + c0, lo);
+      for (int m = 0; m < Coef<Q>::NB; ++m) b[m] = ld_stream<NTP>(&at(prep, (D + 2 + Q + m) * g.plane + c0, lo));
 #pragma unroll
       for (int i = 0; i < Q; ++i) lam[i] += sd * quad_eval<Q, T>(b, i);
     }
@@ -2308,6 +2308,21 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(const Geo g, const ObjBo
   if (!valid) return;
   adjoint_cell<Q, SA, false, HRR, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
                                              tile_lo);
+}
+// The odd step above the Infinity Cache: plain accesses to phi, streaming
+// hints on the frozen per-cell data, which is the cell's own and read once
+// per sweep (2-6 % faster than plain loads on the 8192 x 4096 and
+// 768 x 384 x 128 lattices).
+template <int Q, typename SA, bool HRR, bool MEA>
+__global__ __launch_bounds__(256) void k_adjoint_pstream(const Geo g, const ObjBox ob, const AdjC ac,
+                                                         SA* __restrict__ A, const SA* __restrict__ prep,
+                                                         const double* __restrict__ src,
+                                                         const double* __restrict__ oprep,
+                                                         const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
+  SWEEP_PROLOGUE_TILES
+  if (!valid) return;
+  adjoint_cell<Q, SA, true, HRR, MEA, false, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z,
+                                                   tile_c0, tile_lo);
 }
 
 struct PackedAdjoint {

@@ -391,36 +391,33 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L) {
   const bool odd = (L->adj_iters & 1) != 0;
   const bool hrr = L->desc.collision == HLBM_COLL_HRR, mea = L->obj_kind == HLBM_OBJ_MEA;
   const dim3 grid = tile_grid(L);
-#define HLBM_ADJ(ODD, HRR, MEA)                                                                        \
-  k_adjoint<Q, SA, ODD, HRR, MEA><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, \
-                                                                   pout)
-  if (!odd && L->stream_nt) {  // streaming hints: even step, lattices above the Infinity Cache
+#define HLBM_ADJ(KERNEL, ...) \
+  KERNEL<Q, SA, __VA_ARGS__><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout)
+  // Streaming hints above the Infinity Cache: on phi and the frozen data in
+  // the even step, on the frozen data only in the odd step.
+  if (L->stream_nt && !odd) {
     if (hrr) {
-      if (mea)
-        k_adjoint_stream<Q, SA, true, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
-                                                                             pin, pout);
-      else
-        k_adjoint_stream<Q, SA, true, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
-                                                                              pin, pout);
+      if (mea) HLBM_ADJ(k_adjoint_stream, true, true); else HLBM_ADJ(k_adjoint_stream, true, false);
     } else {
-      if (mea)
-        k_adjoint_stream<Q, SA, false, true><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep,
-                                                                              pin, pout);
-      else
-        k_adjoint_stream<Q, SA, false, false><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src,
-                                                                               L->oprep, pin, pout);
+      if (mea) HLBM_ADJ(k_adjoint_stream, false, true); else HLBM_ADJ(k_adjoint_stream, false, false);
+    }
+  } else if (L->stream_nt) {
+    if (hrr) {
+      if (mea) HLBM_ADJ(k_adjoint_pstream, true, true); else HLBM_ADJ(k_adjoint_pstream, true, false);
+    } else {
+      if (mea) HLBM_ADJ(k_adjoint_pstream, false, true); else HLBM_ADJ(k_adjoint_pstream, false, false);
     }
   } else if (hrr) {
     if (mea) {
-      if (odd) HLBM_ADJ(true, true, true); else HLBM_ADJ(false, true, true);
+      if (odd) HLBM_ADJ(k_adjoint, true, true, true); else HLBM_ADJ(k_adjoint, false, true, true);
     } else {
-      if (odd) HLBM_ADJ(true, true, false); else HLBM_ADJ(false, true, false);
+      if (odd) HLBM_ADJ(k_adjoint, true, true, false); else HLBM_ADJ(k_adjoint, false, true, false);
     }
   } else {
     if (mea) {
-      if (odd) HLBM_ADJ(true, false, true); else HLBM_ADJ(false, false, true);
+      if (odd) HLBM_ADJ(k_adjoint, true, false, true); else HLBM_ADJ(k_adjoint, false, false, true);
     } else {
-      if (odd) HLBM_ADJ(true, false, false); else HLBM_ADJ(false, false, false);
+      if (odd) HLBM_ADJ(k_adjoint, true, false, false); else HLBM_ADJ(k_adjoint, false, false, false);
     }
   }
 #undef HLBM_ADJ

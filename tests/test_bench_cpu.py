@@ -26,6 +26,7 @@ def test_kernel_names_map_to_sweep_kinds():
         "void hlbm::k_primal_wstream<19, float, true, 3, false>(hlbm::Geo)": ("primal_window", "true"),
         "void hlbm::k_adjoint<19, float, true, false, false>(hlbm::Geo)": ("adjoint", "true"),
         "void hlbm::k_adjoint_stream<9, double, false, false>(hlbm::Geo)": ("adjoint", "false"),
+        "void hlbm::k_adjoint_pstream<19, float, false, false>(hlbm::Geo)": ("adjoint", "true"),
         "void hlbm::k_window_region<19, float, false>(hlbm::Geo)": ("region", None),
         "_ZN4hlbm12k_copy_probeILi19EDF16_Lb1ELb1EEEvNS_3GeoE": ("copy_odd_nt", None),
         "void hlbm::k_copy_probe<9, float, false, false>(hlbm::Geo)": ("copy_own", None),
