@@ -1888,7 +1888,7 @@ __device__ __forceinline__ void hrr_phi_moments(const T (&ph)[Q], T& m0, T (&m1)
   }
 }
 
-template <int Q, typename T>
+template <int Q, typename T, bool NT = false>
 __device__ __forceinline__ void sym_read(const T* __restrict__ p, int64_t plane, int64_t cell, int base,
                                          T (&M)[3][3]) {
   const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
@@ -1900,13 +1900,15 @@ __device__ __forceinline__ void sym_read(const T* __restrict__ p, int64_t plane,
   for (int m6 = 0; m6 < 6; ++m6) {
     const int m = sym_index<Q>(m6);
     if (m < 0) continue;
-    const T v = p[(base + m) * plane + cell];
+    const T v = ld_stream<NT>(&p[(base + m) * plane + cell]);
     M[ia[m6]][ib[m6]] = v;
     M[ib[m6]][ia[m6]] = v;
   }
 }
 
-template <int Q, typename T>
+// NT: streaming hints on the frozen per-cell data (lattices above the
+// Infinity Cache, both adjoint steps).
+template <int Q, typename T, bool NT = false>
 __device__ __forceinline__ void hrr_adjoint(const T (&ph)[Q], const T* __restrict__ prep, int64_t plane,
                                             int64_t cell, bool diff, T (&lam)[Q]) {
   using L = Lat<Q>;
@@ -1914,14 +1916,14 @@ __device__ __forceinline__ void hrr_adjoint(const T (&ph)[Q], const T* __restric
   constexpr int D = L::D;
   T m0, m1[3], M2[3][3], M3[H::N];
   hrr_phi_moments<Q, T>(ph, m0, m1, M2, M3);
-  const T rho = prep[cell];
+  const T rho = ld_stream<NT>(&prep[cell]);
   T j[3] = {0, 0, 0};
 #pragma unroll
-  for (int a = 0; a < D; ++a) j[a] = prep[(1 + a) * plane + cell];
-  const T d = prep[(D + 1) * plane + cell];
-  const T omega = prep[(D + 2) * plane + cell];
+  for (int a = 0; a < D; ++a) j[a] = ld_stream<NT>(&prep[(1 + a) * plane + cell]);
+  const T d = ld_stream<NT>(&prep[(D + 1) * plane + cell]);
+  const T omega = ld_stream<NT>(&prep[(D + 2) * plane + cell]);
   T a2[3][3];
-  sym_read<Q, T>(prep, plane, cell, D + 3, a2);
+  sym_read<Q, T, NT>(prep, plane, cell, D + 3, a2);
   const T ir = (T)1 / rho;
   const T u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
   const T ut[3] = {d * u[0], d * u[1], d * u[2]};
@@ -1982,7 +1984,7 @@ __device__ __forceinline__ void hrr_adjoint(const T (&ph)[Q], const T* __restric
   }
   if (diff) {  // omega = 1/tau_eff(Pi), Pi = S - rho/3 I - j j / rho
     T q[3][3];
-    sym_read<Q, T>(prep, plane, cell, D + 3 + L::NSYM, q);
+    sym_read<Q, T, NT>(prep, plane, cell, D + 3 + L::NSYM, q);
     T qu[3], uqu = 0, trq = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -2129,7 +2131,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo& g, const ObjBox& ob, con
   }
   T lam[Q];
   if constexpr (HRR) {
-    hrr_adjoint<Q, T>(ph, prep, g.plane, cell, ac.diff != 0, lam);
+    hrr_adjoint<Q, T, NTP>(ph, prep, g.plane, cell, ac.diff != 0, lam);
   } else {
     // Weighted moments of phi (phi_i = ph[opp i], xi_opp(k) = -xi_k) over the
     // opposite pairs: m0 = sum w phi, m1 = sum w phi xi, M2 = sum w phi xi xi;
