@@ -128,10 +128,12 @@ typedef enum {
  * closure (smagorinsky_cs > 0). */
 typedef enum { HLBM_COLL_BGK = 0, HLBM_COLL_HRR = 1 } hlbm_collision;
 
-/* Cache hints of the population loads and stores of the sweeps: both AA
+/* Cache hints of the sweeps: the population loads and stores of both AA
  * steps of the D2Q9 primal sweep (with or without the window statistics),
- * the even step of the D3Q19 primal sweep (its odd step reuses the lines of
- * the neighbouring xy layer) and the even step of the adjoint sweep.
+ * of the even step of the D3Q19 primal sweep (its odd step reuses the lines
+ * of the neighbouring xy layer) and of the even step of the adjoint sweep;
+ * the window sums of every window step and the adjoint's frozen per-cell
+ * data in both adjoint steps (data of the cell's own, read once a sweep).
  * AUTO: streaming (nontemporal) hints when the populations and the porosity
  * exceed 256 MiB, the size of the MI355X Infinity Cache, plain accesses
  * otherwise (a lattice that stays in that cache from one step to the next
