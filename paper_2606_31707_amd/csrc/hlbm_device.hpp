@@ -219,9 +219,10 @@ __device__ __forceinline__ double block_max256(double v, double* lds) {
 // boundary path) start first rather than last (2 % per step on the
 // 1100 x 410 channel; on larger grids the reversed walk measured 2-4 %
 // slower).  b -> tile is a bijection of [0, nt): the last XCD's range has q
-// tiles (r < NXCD) and k < q there.
-__device__ __forceinline__ int sweep_tile(int b, int nt) {
-  if (!HLBM_XCD_REMAP) return b;
+// tiles (r < NXCD) and k < q there.  remap = false keeps the dispatch order
+// (see runs_remap).
+__device__ __forceinline__ int sweep_tile(int b, int nt, bool remap = true) {
+  if (!HLBM_XCD_REMAP || !remap) return b;
   const int q = nt / NXCD, r = nt % NXCD;
   const int xcd = b % NXCD, k = b / NXCD;
   const int start = xcd * q + (xcd < r ? xcd : r);

@@ -646,8 +646,21 @@ __device__ __forceinline__ bool sweep_cell(const Geo& g, uint32_t c0, uint32_t l
   return z < g.nz;
 }
 
+// Whether the runs of a plain step (population type S) take the XCD
+// renumbering of sweep_tile.  D2Q9: yes (its odd step's x-neighbouring runs
+// share cache lines).  D3Q19: only the FP64 odd step; the even steps and the
+// FP32/FP16S odd steps keep the dispatch order, in which the XCDs sweep
+// neighbouring runs at the same time (768 x 384 x 128, per step: FP16S even
+// 596 -> 544 us, odd 667 -> 635; FP32 even 1121 -> 1094, odd 1150 -> 1127;
+// FP64 even 2285 -> 2223, odd 2323 -> 2557 without the renumbering, which is
+// why it stays there; in D2Q9 the dispatch order measured -2 % to +6 %).
+template <int Q, typename S, bool ODD>
+__device__ __forceinline__ constexpr bool runs_remap() {
+  return Lat<Q>::D == 2 || (ODD && sizeof(S) == 8);
+}
+
 #define SWEEP_PROLOGUE_RUNS                                                   \
-  const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x);                 \
+  const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x, runs_remap<Q, S, ODD>()); \
   const int64_t tile_c0 = (int64_t)t_ * SWEEP_BLOCK;                          \
   const uint32_t tile_lo = lane_offset(threadIdx.x);                          \
   int x, y, z;                                                                \
@@ -1187,6 +1200,7 @@ __global__ __launch_bounds__(256) void k_tangent(const Geo g, const Coll c, doub
                                                  double* __restrict__ At, const double* __restrict__ dpor,
                                                  const double* __restrict__ v, double* __restrict__ ghost,
                                                  double* __restrict__ ghostt) {
+  using S = double;  // the tile order of an FP64 plain step
   SWEEP_PROLOGUE_RUNS
   if (!valid) return;
   tangent_cell<Q, ODD>(g, c, A, At, dpor, v, ghost, ghostt, x, y, z);
