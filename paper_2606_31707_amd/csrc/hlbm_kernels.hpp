@@ -623,11 +623,12 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
 //    64 cells run along a row and continue on the next row where one ends.
 //    The block's first cell is uniform; its coordinates come from two uniform
 //    divisions and each lane steps on from there.  No lanes are lost to
-//    ragged row ends.  Used by the plain primal step and the tangent:
-//    measured -9 % on the even, +1.5 % on the odd step, -2 % per pair on the
-//    1100 x 410 lattice, unchanged on large lattices;
+//    ragged row ends.  Used by the plain primal step and the tangent
+//    (measured -9 % on the even, +1.5 % on the odd step, -2 % per pair on the
+//    1100 x 410 lattice) and by the D3Q19 FP32/FP16 window steps and adjoint
+//    (sweep_runs, adjoint_runs);
 //  * tiles (SWEEP_PROLOGUE_TILES): 128 x 2 tiles of two half-rows.  Used by
-//    the window steps and the adjoint, which measured 3-4 % slower with runs.
+//    the other window steps and adjoints (D2Q9: 3-4 % slower with runs).
 __device__ __forceinline__ bool sweep_cell(const Geo& g, uint32_t c0, uint32_t lane, int& x, int& y, int& z) {
   const uint32_t nxy = (uint32_t)g.nx * (uint32_t)g.ny;
   const uint32_t z0 = (uint32_t)wave_uniform((int)(c0 / nxy));
@@ -646,21 +647,38 @@ __device__ __forceinline__ bool sweep_cell(const Geo& g, uint32_t c0, uint32_t l
   return z < g.nz;
 }
 
-// Whether the runs of a plain step (population type S) take the XCD
-// renumbering of sweep_tile.  D2Q9: yes (its odd step's x-neighbouring runs
-// share cache lines).  D3Q19: only the FP64 odd step; the even steps and the
-// FP32/FP16S odd steps keep the dispatch order, in which the XCDs sweep
-// neighbouring runs at the same time (768 x 384 x 128, per step: FP16S even
-// 596 -> 544 us, odd 667 -> 635; FP32 even 1121 -> 1094, odd 1150 -> 1127;
-// FP64 even 2285 -> 2223, odd 2323 -> 2557 without the renumbering, which is
-// why it stays there; in D2Q9 the dispatch order measured -2 % to +6 %).
-template <int Q, typename S, bool ODD>
-__device__ __forceinline__ constexpr bool runs_remap() {
-  return Lat<Q>::D == 2 || (ODD && sizeof(S) == 8);
+// Lane map and tile order of the sweeps, chosen per stencil and precision by
+// measurement on 768 x 384 x 128 (D3Q19) and 8192 x 4096 (D2Q9):
+//  * sweep_runs: runs for every plain step, and for the window steps of D3Q19
+//    with FP32/FP16 populations (window sweep 1717 -> 1695 us FP32,
+//    1174 -> 1121 FP16S against 128 x 2 tiles; FP64 +1 %: tiles stay);
+//  * runs_remap: the XCD renumbering of sweep_tile for D2Q9 runs (its odd
+//    step's x-neighbouring runs share cache lines) and for the D3Q19 FP64 odd
+//    plain step; every other D3Q19 run keeps the dispatch order, in which the
+//    XCDs sweep neighbouring runs at the same time (per plain step: FP16S
+//    even 596 -> 544 us, odd 667 -> 635; FP32 1121 -> 1094, 1150 -> 1127;
+//    FP64 even 2285 -> 2223, but odd 2323 -> 2557, so that one keeps it; in
+//    D2Q9 the dispatch order measured -2 % to +6 %);
+//  * adjoint_runs: the D3Q19 adjoint with an FP32 adjoint state takes runs in
+//    dispatch order (FP32 1244 -> 1194 us, FP16S lattices 1245 -> 1185;
+//    FP64 +0.5 %: tiles stay).
+// Tiles always take the renumbering (the dispatch order measured 2-13 %
+// slower for them).
+template <int Q, typename S, int ACC>
+__host__ __device__ constexpr bool sweep_runs() {
+  return ACC == 0 || (Lat<Q>::D == 3 && sizeof(S) <= 4);
+}
+template <int Q, typename S, bool ODD, int ACC>
+__host__ __device__ constexpr bool runs_remap() {
+  return Lat<Q>::D == 2 || (ACC == 0 && ODD && sizeof(S) == 8);
+}
+template <int Q, typename SA>
+__host__ __device__ constexpr bool adjoint_runs() {
+  return Lat<Q>::D == 3 && sizeof(SA) == 4;
 }
 
-#define SWEEP_PROLOGUE_RUNS                                                   \
-  const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x, runs_remap<Q, S, ODD>()); \
+#define SWEEP_PROLOGUE_RUNS(REMAP)                                            \
+  const int t_ = sweep_tile((int)blockIdx.x, (int)gridDim.x, (REMAP));        \
   const int64_t tile_c0 = (int64_t)t_ * SWEEP_BLOCK;                          \
   const uint32_t tile_lo = lane_offset(threadIdx.x);                          \
   int x, y, z;                                                                \
@@ -975,8 +993,8 @@ template <int Q, typename S, bool ODD, int ACC, bool HRR, bool NT, bool NTW = NT
 __device__ __forceinline__ void primal_sweep(const Geo& g, const Coll& c, const ObjBox& ob, S* __restrict__ A,
                                              const typename Prec<S>::Dd* __restrict__ dpor,
                                              S* __restrict__ ghost, const Acc& acc) {
-  if constexpr (ACC == 0) {
-    SWEEP_PROLOGUE_RUNS
+  if constexpr (sweep_runs<Q, S, ACC>()) {
+    SWEEP_PROLOGUE_RUNS((runs_remap<Q, S, ODD, ACC>()))
     if (!valid) return;
     primal_cell<Q, S, ODD, ACC, HRR, NT, NTW>(g, c, ob, A, dpor, ghost, acc, x, y, z, tile_c0, tile_lo);
   } else {
@@ -1029,7 +1047,7 @@ template <int Q, typename S, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_copy_probe(const Geo g, S* __restrict__ A,
                                                     const typename Prec<S>::Dd* __restrict__ dpor,
                                                     int* __restrict__ sink) {
-  SWEEP_PROLOGUE_RUNS
+  SWEEP_PROLOGUE_RUNS((runs_remap<Q, S, ODD, 0>()))  // the plain step's order
   if (!valid) return;
   const auto d = at(dpor, tile_c0, tile_lo);
   S v[Q];
@@ -1200,8 +1218,7 @@ __global__ __launch_bounds__(256) void k_tangent(const Geo g, const Coll c, doub
                                                  double* __restrict__ At, const double* __restrict__ dpor,
                                                  const double* __restrict__ v, double* __restrict__ ghost,
                                                  double* __restrict__ ghostt) {
-  using S = double;  // the tile order of an FP64 plain step
-  SWEEP_PROLOGUE_RUNS
+  SWEEP_PROLOGUE_RUNS((runs_remap<Q, double, ODD, 0>()))  // the order of an FP64 plain step
   if (!valid) return;
   tangent_cell<Q, ODD>(g, c, A, At, dpor, v, ghost, ghostt, x, y, z);
 }
@@ -2306,9 +2323,15 @@ __global__ __launch_bounds__(256) void k_adjoint(const Geo g, const ObjBox ob, c
                                                  const double* __restrict__ src,
                                                  const double* __restrict__ oprep,
                                                  const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
-  SWEEP_PROLOGUE_TILES
-  if (!valid) return;
-  adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
+  if constexpr (adjoint_runs<Q, SA>()) {
+    SWEEP_PROLOGUE_RUNS(false)
+    if (!valid) return;
+    adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
+  } else {
+    SWEEP_PROLOGUE_TILES
+    if (!valid) return;
+    adjoint_cell<Q, SA, ODD, HRR, MEA>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0, tile_lo);
+  }
 }
 
 // The even adjoint step with streaming hints on the phi accesses (lattices
@@ -2320,10 +2343,17 @@ __global__ __launch_bounds__(256) void k_adjoint_stream(const Geo g, const ObjBo
                                                         const double* __restrict__ src,
                                                         const double* __restrict__ oprep,
                                                         const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
-  SWEEP_PROLOGUE_TILES
-  if (!valid) return;
-  adjoint_cell<Q, SA, false, HRR, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
-                                             tile_lo);
+  if constexpr (adjoint_runs<Q, SA>()) {
+    SWEEP_PROLOGUE_RUNS(false)
+    if (!valid) return;
+    adjoint_cell<Q, SA, false, HRR, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
+                                               tile_lo);
+  } else {
+    SWEEP_PROLOGUE_TILES
+    if (!valid) return;
+    adjoint_cell<Q, SA, false, HRR, MEA, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z, tile_c0,
+                                               tile_lo);
+  }
 }
 // The odd step above the Infinity Cache: plain accesses to phi, streaming
 // hints on the frozen per-cell data, which is the cell's own and read once
@@ -2335,10 +2365,17 @@ __global__ __launch_bounds__(256) void k_adjoint_pstream(const Geo g, const ObjB
                                                          const double* __restrict__ src,
                                                          const double* __restrict__ oprep,
                                                          const SA* __restrict__ pv_in, SA* __restrict__ pv_out) {
-  SWEEP_PROLOGUE_TILES
-  if (!valid) return;
-  adjoint_cell<Q, SA, true, HRR, MEA, false, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z,
-                                                   tile_c0, tile_lo);
+  if constexpr (adjoint_runs<Q, SA>()) {
+    SWEEP_PROLOGUE_RUNS(false)
+    if (!valid) return;
+    adjoint_cell<Q, SA, true, HRR, MEA, false, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z,
+                                                     tile_c0, tile_lo);
+  } else {
+    SWEEP_PROLOGUE_TILES
+    if (!valid) return;
+    adjoint_cell<Q, SA, true, HRR, MEA, false, true>(g, ob, ac, A, prep, src, oprep, pv_in, pv_out, x, y, z,
+                                                     tile_c0, tile_lo);
+  }
 }
 
 struct PackedAdjoint {

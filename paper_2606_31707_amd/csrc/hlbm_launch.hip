@@ -87,8 +87,9 @@ static void primal_variant(hlbm_lattice_s* L) {
   S* A = (S*)L->f;
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
-  const dim3 grid = ACC == 0 ? sweep_grid(L) : tile_grid(L);
-  const dim3 block = ACC == 0 ? kSweepBlock : kBlock;
+  constexpr bool runs = sweep_runs<Q, S, ACC>();  // lane map of the sweep (runs or tiles)
+  const dim3 grid = runs ? sweep_grid(L) : tile_grid(L);
+  const dim3 block = runs ? kSweepBlock : kBlock;
   // Streaming hints (lattices above the Infinity Cache): both D2Q9 steps;
   // only the D3Q19 even step, whose accesses are the cell's own slots (the
   // odd step's z neighbours reuse lines one xy layer later and ran 7 %
@@ -390,9 +391,11 @@ static hipError_t adjoint_impl(hlbm_lattice_s* L) {
   const SA* prep = (const SA*)L->prep;
   const bool odd = (L->adj_iters & 1) != 0;
   const bool hrr = L->desc.collision == HLBM_COLL_HRR, mea = L->obj_kind == HLBM_OBJ_MEA;
-  const dim3 grid = tile_grid(L);
+  constexpr bool runs = adjoint_runs<Q, SA>();  // lane map of the sweep (runs or tiles)
+  const dim3 grid = runs ? sweep_grid(L) : tile_grid(L);
+  const dim3 block = runs ? kSweepBlock : kBlock;
 #define HLBM_ADJ(KERNEL, ...) \
-  KERNEL<Q, SA, __VA_ARGS__><<<grid, kBlock, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout)
+  KERNEL<Q, SA, __VA_ARGS__><<<grid, block, 0, L->stream>>>(g, ob, ac, A, prep, L->src, L->oprep, pin, pout)
   // Streaming hints above the Infinity Cache: on phi and the frozen data in
   // the even step, on the frozen data only in the odd step.
   if (L->stream_nt && !odd) {
