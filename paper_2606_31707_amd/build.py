@@ -1,7 +1,8 @@
 """Builds libhlbm.so (gfx950 HIP kernels + C ABI) in-tree with hipcc, and
-libhlbm_canary.so, the same sources with 64 x 4 tiles and no XCD tile
-remapping (the race canary: every per-cell result must be bitwise the same
-under another tile shape and workgroup order)."""
+libhlbm_canary.so, the same sources with 64 x 4 tiles and every sweep's
+workgroup order flipped (XCD-renumbered where the default keeps the dispatch
+order and the other way round): the race canary, under which every per-cell
+result must be bitwise the same."""
 from __future__ import annotations
 
 import os

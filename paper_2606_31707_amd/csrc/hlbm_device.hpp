@@ -19,6 +19,9 @@ enum { NB_CELL = 0, NB_BOUNCE = 1, NB_OUTLET = 2, NB_DROP = 3 };
 #ifndef HLBM_TILE_BX
 #define HLBM_TILE_BX 128
 #endif
+// 1: the tuned workgroup orders (sweep_tile); 0: every order flipped
+// (renumbered where the tuned build keeps the dispatch order and the other
+// way round) -- the race-canary build.
 #ifndef HLBM_XCD_REMAP
 #define HLBM_XCD_REMAP 1
 #endif
@@ -220,9 +223,9 @@ __device__ __forceinline__ double block_max256(double v, double* lds) {
 // 1100 x 410 channel; on larger grids the reversed walk measured 2-4 %
 // slower).  b -> tile is a bijection of [0, nt): the last XCD's range has q
 // tiles (r < NXCD) and k < q there.  remap = false keeps the dispatch order
-// (see runs_remap).
+// (see runs_remap); the canary build flips the choice.
 __device__ __forceinline__ int sweep_tile(int b, int nt, bool remap = true) {
-  if (!HLBM_XCD_REMAP || !remap) return b;
+  if (HLBM_XCD_REMAP ? !remap : remap) return b;
   const int q = nt / NXCD, r = nt % NXCD;
   const int xcd = b % NXCD, k = b / NXCD;
   const int start = xcd * q + (xcd < r ? xcd : r);

@@ -1,5 +1,6 @@
 """Race canary: the library built with another tile shape (64 x 4 instead of
-128 x 2) and the default workgroup order (no XCD remapping) must give bitwise
+128 x 2) and every sweep's workgroup order flipped (XCD-renumbered where the
+default keeps the dispatch order, and the other way round) must give bitwise
 the same per-cell results -- populations, window means, adjoint populations,
 gradients -- in every precision and for both collisions, because every slot
 is read and written by exactly one thread per step.  A dependence on
