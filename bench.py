@@ -457,6 +457,50 @@ def kernel_kind(name: str):
     return None, None
 
 
+def les_dispatches(trace_dir: str, w, short):
+    """Total duration, launch count and kernels per sweep kind of the
+    dispatches on lattice `w` in a rocprofv3 kernel trace: sweeps with a grid
+    of at least half the lattice's cells, region passes with the grid of w's
+    objective region (rounded up to whole workgroups).  The reduced record is
+    kept beside the trace (les_dispatches.json) so that the summary can be
+    redone without the full trace file."""
+    import csv
+    cache = os.path.join(trace_dir, "les_dispatches.json")
+    path = os.path.join(trace_dir, "bench_kernel_trace.csv")
+    if not os.path.exists(path):
+        return json.load(open(cache))
+    region = int(np.prod([h - l + 1 for l, h in zip(w.lo, w.hi)]))
+    region_grid = -(-region // 256) * 256
+    acc = {}
+    per_kernel = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = short(r["Kernel_Name"])
+            kind, _ = kernel_kind(name)
+            if kind is None:
+                continue
+            if "Grid_Size" in r:
+                grid = int(r["Grid_Size"])
+            else:
+                grid = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y") or 1) * int(r.get("Grid_Size_Z") or 1)
+            if kind == "region" and grid != region_grid:
+                continue
+            if kind != "region" and grid < w.n // 2:
+                continue
+            ns = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+            a = acc.setdefault(kind, {"ns": 0.0, "calls": 0, "kernels": []})
+            a["ns"] += ns
+            a["calls"] += 1
+            k = per_kernel.setdefault((kind, name), [0.0, 0])
+            k[0] += ns
+            k[1] += 1
+    for (kind, name), (ns, calls) in sorted(per_kernel.items()):
+        acc[kind]["kernels"].append(f"`{name}` {calls} x {ns / calls / 1e3:.1f} us")
+    with open(cache, "w") as fh:
+        json.dump(acc, fh, indent=1)
+    return acc
+
+
 def summarize_profiles(d: str):
     """Writes the profiles/ summaries from the rocprofv3 CSV output under `d`
     (made by the profile_commands): the benchmark's kernel trace with its
@@ -485,7 +529,11 @@ def summarize_profiles(d: str):
              if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
         return float(np.mean(v))
 
-    cf, cw = copy_kib("copy_FETCH_SIZE", "FETCH_SIZE"), copy_kib("copy_WRITE_SIZE", "WRITE_SIZE")
+    try:
+        cf, cw = copy_kib("copy_FETCH_SIZE", "FETCH_SIZE"), copy_kib("copy_WRITE_SIZE", "WRITE_SIZE")
+    except OSError as e:  # no calibration runs under d: the benchmark trace only
+        log(f"calibration: {e}")
+        cf = cw = float("nan")
     ff, wf = 512 * 1024 / cf, 512 * 1024 / cw
     traffic = {"kernel_source_sha256": kernel_source_hash(),
                "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 512 MiB)", "fetch_kib": cf,
@@ -527,7 +575,7 @@ def summarize_profiles(d: str):
             a[1] += 1
         return acc
 
-    for case in SWEEP_CASES:
+    for case in SWEEP_CASES if np.isfinite(cf) else ():
         rep = None
         try:
             for line in open(os.path.join(d, case, "report.json")):
@@ -604,7 +652,9 @@ def summarize_profiles(d: str):
             live = json.load(open(os.path.join(d, "bench.json")))
         except (OSError, ValueError):
             pass
-        acc = per_kind([r for r in stats if "<19, float" in r["Name"]])
+        # per-launch figures from the LES lattice's own dispatches (the serving
+        # stream's small D3Q19 lattices run some of the same kernels)
+        acc = les_dispatches(os.path.join(d, "bench_trace"), I.les_re3900(), short)
         lines = ["# Kernel trace of the benchmark command (les_re3900_768x384x128, D3Q19 FP32)", "",
                  "Command (run from the repository root on the MI355X box, `export TMPDIR=/tmp`):", "", "```",
                  cmds["bench_trace"], "```", "",
@@ -615,14 +665,20 @@ def summarize_profiles(d: str):
             lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                          f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                          f"{float(r['Percentage']):.2f} |")
-        lines += ["", "Per launch of each LES sweep kind (trace durations; a window step = its sweep + the region pass):", ""]
+        lines += ["", "Per launch of each LES sweep kind (trace durations of the dispatches on the LES lattice, "
+                      "selected by grid size; a window step = its sweep + the region pass):", ""]
         w = I.les_re3900()
         for kind in ("primal", "primal_window", "adjoint"):
             us = launch_us(acc, kind)
+            if us is None:
+                continue
             ev = live["sweeps"][kind]["us_per_launch"] if live else None
             lines.append(f"- {kind}: {us:.1f} us per launch (trace)" +
                          (f"; the benchmark's own HIP-event figure in an unprofiled run of the same command: "
                           f"{ev:.1f} us" if ev else ""))
+        for kind in ("primal", "primal_window", "adjoint", "region"):
+            if kind in acc:
+                lines.append(f"  - {kind}: " + "; ".join(acc[kind]["kernels"]))
         if live:
             lines += ["", f"Dominant sweep of the benchmark line: {live['roofline']['kind']} "
                           f"({live['roofline']['achieved']:.0f} GB/s algorithmic, frac {live['roofline']['frac']:.3f})."]

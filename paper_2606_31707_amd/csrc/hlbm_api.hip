@@ -161,6 +161,12 @@ hlbm_status ensure_window(hlbm_lattice_s* L) {
   if (L->desc.track_mean_populations && (s = lat_alloc(L, (void**)&L->acc_f, sizeof(double) * P * L->q)) != HLBM_OK)
     return s;
   if (L->desc.smagorinsky_cs > 0.0 && (s = lat_alloc(L, (void**)&L->acc_tau, sizeof(double) * P)) != HLBM_OK) return s;
+  // FP32 arithmetic: the pending planes of the paired accumulation (written
+  // by an odd window step before they are read)
+  if (L->desc.precision != HLBM_FP64 &&
+      (s = lat_alloc(L, (void**)&L->acc_pend,
+                     sizeof(float) * P * (2 + L->dim + (L->desc.track_mean_populations ? L->q : 0)))) != HLBM_OK)
+    return s;
   if (fresh) {
     HIP_TRY(hipMemsetAsync(L->acc_rho, 0, sizeof(double) * P, L->stream));
     HIP_TRY(hipMemsetAsync(L->acc_j, 0, sizeof(double) * P * L->dim, L->stream));
@@ -209,6 +215,16 @@ hlbm_status zero_window(hlbm_lattice_s* L) {
   if (L->acc_tau) HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * P, L->stream));
   if (L->acc_obj) HIP_TRY(hipMemsetAsync(L->acc_obj, 0, sizeof(double) * L->rplane * L->ncoef, L->stream));
   L->nsamp = 0;
+  L->pend_valid = 0;
+  return HLBM_OK;
+}
+
+// Completes the paired accumulation of a run that ended after an odd window
+// step (the sums are whole again outside hlbm_run_primal).
+hlbm_status flush_window(hlbm_lattice_s* L) {
+  if (!L->pend_valid) return HLBM_OK;
+  L->pend_valid = 0;
+  HIP_TRY(launch_window_flush(L));
   return HLBM_OK;
 }
 
@@ -383,7 +399,7 @@ hlbm_status hlbm_create(const hlbm_desc* desc, hlbm_lattice* out) {
 void hlbm_destroy(hlbm_lattice L) {
   if (!L) return;
   (void)hipStreamSynchronize(L->stream);
-  void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj,
+  void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj, L->acc_pend,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
                   L->red, L->usnap, L->probe_buf, L->mea_flag, L->mea_src, L->tan_f, L->tan_ghost,
                   L->tan_v, L->tan_rec};
@@ -708,6 +724,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
       if ((s = reduce_to_host(L, nbl, 1, mm)) != HLBM_OK) return s;
       if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) {
         if (steps_done) *steps_done = done;
+        if ((s = flush_window(L)) != HLBM_OK) return s;
         return fail(HLBM_E_DIVERGED, "non-finite velocity after %lld steps", (long long)L->steps);
       }
       if (mm[0] <= steady_tol * mm[1]) {
@@ -717,6 +734,7 @@ hlbm_status hlbm_run_primal(hlbm_lattice L, int64_t n_steps, int32_t accumulate,
     }
   }
   if (steps_done) *steps_done = done;
+  if ((s = flush_window(L)) != HLBM_OK) return s;
   if (steady_tol > 0.0 && !converged) result = HLBM_W_NOT_CONVERGED;
   L->adj_ready = 0;
   return result;
@@ -978,10 +996,14 @@ extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, dou
   const bool smag = L->desc.smagorinsky_cs > 0.0;
   // primal: read + write every population once, read d
   const double p = 2.0 * q * ss + ds;
-  // window: FP64 read-modify-write of rho, j (+ f, tau) and the region terms
-  double pw = p + 16.0 * (1.0 + dim);
-  if (L->desc.track_mean_populations) pw += 16.0 * q;
-  if (smag) pw += 16.0;
+  // window: FP64 read-modify-write of the m dense sums rho, j (+ f, tau) and
+  // the region terms; with the paired accumulation (FP32 arithmetic) one
+  // read-modify-write per pair of steps, the odd step writing m FP32 values
+  // that the even step reads: 12 m per step instead of 16 m
+  double m = 1.0 + dim;
+  if (L->desc.track_mean_populations) m += q;
+  if (smag) m += 1.0;
+  double pw = p + (L->desc.precision != HLBM_FP64 ? 12.0 : 16.0) * m;
   pw += rfrac * 16.0 * L->ncoef;
   // adjoint: read + write phi, read the frozen coefficients and the source
   const double nsym = dim == 2 ? 3.0 : 6.0;

@@ -85,6 +85,8 @@ inline const char* footprint_of(const hlbm_desc* desc, int with_window, int with
     b += P * 8 * (1 + dim);
     if (desc->track_mean_populations) b += P * 8 * q;
     if (desc->smagorinsky_cs > 0) b += P * 8;
+    // FP32 pending values of the paired accumulation
+    if (desc->precision != HLBM_FP64) b += P * 4 * (2 + dim + (desc->track_mean_populations ? q : 0));
   }
   if (with_adjoint) {
     b += P * as * q;                                    // phi

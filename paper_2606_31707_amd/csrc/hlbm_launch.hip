@@ -84,6 +84,13 @@ static void primal_variant(hlbm_lattice_s* L) {
   const ObjBox ob = make_obj(L);
   Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
           c.smag ? L->acc_tau : nullptr, L->acc_obj};
+  if constexpr (ACC != 0) {  // paired window accumulation (FP32 and FP16 lattices)
+    if (L->acc_pend) {
+      acc.pend = L->acc_pend;
+      acc.pend_in = (L->parity == 0 && L->pend_valid) ? 1 : 0;
+      L->pend_valid = L->parity == 1;
+    }
+  }
   S* A = (S*)L->f;
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
@@ -170,6 +177,18 @@ static hipError_t primal_impl(hlbm_lattice_s* L, int accumulate) {
 
 hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate) {
   HLBM_DISPATCH(L, primal_impl, L, accumulate);
+}
+
+hipError_t launch_window_flush(hlbm_lattice_s* L) {
+  const Geo g = make_geo(L);
+  Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
+          make_coll(L).smag ? L->acc_tau : nullptr, L->acc_obj};
+  acc.pend = L->acc_pend;
+  if (L->q == 9)
+    k_window_flush<9><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc);
+  else
+    k_window_flush<19><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc);
+  return hipGetLastError();
 }
 
 template <int Q, typename S>

@@ -1,0 +1,69 @@
+"""Paired window accumulation (FP32 and FP16 lattices): an odd window step
+leaves its values (drho, j, tau_eff, f) in FP32 pending planes and the next
+even window step adds them to the FP64 sums before its own, or a flush does
+at the end of a run.  The sums must be bitwise those of launches that add
+every step at once -- the packed group launches, which never pair -- for
+windows that start on either step parity and runs that end on either, with
+the Smagorinsky closure (the tau_eff sum) and the mean populations tracked
+(the f sums, read by the differentiated-closure and HRR adjoints)."""
+import numpy as np
+import pytest
+
+from tests.pairs import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _lattice(H, prec, coll):
+    nx, ny, nz = 48, 24, 16
+    G = H.Lattice(stencil=H.D3Q19, precision=prec, nx=nx, ny=ny, nz=nz, tau=0.52, cs=0.1,
+                  bc_x=H.BC_INLET_OUTLET, bc_y=H.BC_PERIODIC, bc_z=H.BC_PERIODIC, inlet_profile=1, u_in=0.05,
+                  track_mean_populations=True, collision=coll)
+    G.build_cylinder(14.0, 11.5, 7.0)
+    rng = np.random.default_rng(7)
+    G.init_equilibrium(1.0, 0.05 * 0.02 * rng.uniform(-1.0, 1.0, 3 * nx * ny * nz))
+    G.set_objective(H.OBJ_FFA, (30, 2, 0), (30, 21, nz - 1), u0=0.05)
+    return G
+
+
+@pytest.mark.parametrize("prec,coll", [(1, 0), (2, 0), (1, 1)])
+def test_paired_sums_equal_unpaired_launches(prec, coll):
+    from paper_2606_31707_amd import hlbm as H
+    say("paired window", prec, coll)
+    solo, pack = _lattice(H, prec, coll), _lattice(H, prec, coll)
+    # three plain steps: the window starts on an odd step; the runs end on
+    # odd, even and odd steps
+    solo.run_primal(3)
+    for n in (7, 10, 5):
+        solo.run_primal(n, accumulate=True)
+    g = H.Group()
+    g.set([pack], [H.GROUP_PRIMAL])
+    g.step(3)
+    g.set([pack], [H.GROUP_PRIMAL_WINDOW])
+    g.step(22)
+    g.synchronize()
+    assert np.array_equal(solo.populations(), pack.populations())
+    for fld in (H.FIELD_MEAN_RHO, H.FIELD_MEAN_U, H.FIELD_MEAN_TAU):
+        assert np.array_equal(solo.field(fld), pack.field(fld)), fld
+    assert solo.window_objective() == pack.window_objective()
+    # the mean populations enter the adjoint through the differentiated
+    # closure (and the HRR collision's frozen data)
+    for L in (solo, pack):
+        L.solve_adjoint(H.SOURCE_MEAN, tau_adj=0.6, turb=H.TURB_DIFFERENTIATED, max_iters=30)
+    assert np.array_equal(solo.gradient(), pack.gradient())
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_window_bytes_per_update(prec):
+    """Algorithmic bytes of a window step: 16 B per dense FP64 sum and step
+    (read and write), 12 B with the pairing (a read-modify-write per pair of
+    steps plus one FP32 value written and read)."""
+    from paper_2606_31707_amd import hlbm as H
+    G = _lattice(H, prec, 0)
+    bpu = G.bytes_per_update()
+    m = 1 + 3 + 1 + 19  # rho, j, tau_eff, f
+    rfrac = 20 * 16 / G.n
+    per_sum = 16.0 if prec == 0 else 12.0
+    assert bpu["primal_window"] == pytest.approx(bpu["primal"] + per_sum * m + rfrac * 16.0 * 12, rel=1e-12)
+    G.close()
