@@ -575,37 +575,54 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
   // Per opposite pair (k, opp k): xi.u~, xi.j and the third-order terms
   // change sign, the second-order terms do not, so each pair is one
   // symmetric part plus or minus one antisymmetric part; only the nonzero
-  // lattice coefficients enter the sums.
+  // lattice coefficients enter the sums.  With xi.u~ = (d / rho) xi.j, the
+  // per-cell factors are combined once, so that a pair costs one projection
+  // xi.j, the second-order sum xi xi : a2 and one third-order sum:
+  //   sym = w (base2 + kb (xi.j)^2 + kn xi xi : a2),
+  //   asy = w (ka xi.j + sum_t H3_t(xi) c3_t),
+  // base2 = base - kn tr(a2) / 3, kb = 4.5 rho (d/rho)^2, kn = 4.5 (1 - omega),
+  // ka = 3 rho (d/rho) + 3 (1 - omega)(1 - d), c3_t = 13.5 (e3_t + (1 - omega) a3_t):
+  // the equilibrium (base, 3 rho xi.u~, 4.5 rho (xi.u~)^2, 13.5 e3) plus
+  // (1 - omega) times the regularised non-equilibrium part (4.5 xi xi : a2
+  // minus its trace part, 3 (1 - d) xi.j, 13.5 a3).
   const T omd = (T)1 - d, om1 = (T)1 - omega;
+  const T dir = d * ir;
   const T base = drho - (T)1.5 * rho * tt;  // the equilibrium's isotropic part
-  const T ntr = -tr / (T)3;                  // the isotropic part of xi xi : a2
-  const T rho3 = (T)3 * rho, rho45 = (T)4.5 * rho, omd3 = (T)3 * omd;
-  s[0] = (T)L::w[0] * base + om1 * ((T)L::w[0] * (T)4.5 * ntr);
+  const T kn = (T)4.5 * om1;
+  const T base2 = base - kn * (tr / (T)3);   // plus the isotropic part of xi xi : a2
+  const T ka = (T)3 * rho * dir + om1 * ((T)3 * omd);
+  const T kb = (T)4.5 * rho * dir * dir;
+  T c3[H::N];
+#pragma unroll
+  for (int t = 0; t < H::N; ++t) c3[t] = (T)13.5 * (e3c[t] + om1 * a3[t]);
+  s[0] = (T)L::w[0] * base2;
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
     if (L::opp[k] < k) continue;
     const int o = L::opp[k];
-    const T cu = csum<T>(L::cx[k], L::cy[k], L::cz[k], ut[0], ut[1], ut[2]);
     const T cj = csum<T>(L::cx[k], L::cy[k], L::cz[k], jx, jy, jz);
-    T n2 = ntr, e3 = 0, n3 = 0;
+    T m2 = 0, g3 = 0;
+    bool f2 = true, f3 = true;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = 0; b < D; ++b)
-        if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) n2 += (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * a2[a][b];
-    bool first = true;
+        if (lat_c<Q>(k, a) * lat_c<Q>(k, b) != 0) {
+          const T v = (T)(lat_c<Q>(k, a) * lat_c<Q>(k, b)) * a2[a][b];
+          m2 = f2 ? v : m2 + v;
+          f2 = false;
+        }
 #pragma unroll
     for (int t = 0; t < H::N; ++t) {
       const T h = (T)h3<Q>(k, t);
       if (h != (T)0) {
-        e3 = first ? h * e3c[t] : e3 + h * e3c[t];
-        n3 = first ? h * a3[t] : n3 + h * a3[t];
-        first = false;
+        g3 = f3 ? h * c3[t] : g3 + h * c3[t];
+        f3 = false;
       }
     }
     const T w = (T)L::w[k];
-    const T sym = w * (base + rho45 * cu * cu) + om1 * (w * (T)4.5 * n2);
-    const T asy = w * (rho3 * cu + (T)13.5 * e3) + om1 * (w * (omd3 * cj + (T)13.5 * n3));
+    const T sym = w * (base2 + kb * cj * cj + kn * m2);
+    const T asy = w * (ka * cj + g3);
     s[k] = sym + asy;
     s[o] = sym - asy;
   }
