@@ -161,11 +161,10 @@ hlbm_status ensure_window(hlbm_lattice_s* L) {
   if (L->desc.track_mean_populations && (s = lat_alloc(L, (void**)&L->acc_f, sizeof(double) * P * L->q)) != HLBM_OK)
     return s;
   if (L->desc.smagorinsky_cs > 0.0 && (s = lat_alloc(L, (void**)&L->acc_tau, sizeof(double) * P)) != HLBM_OK) return s;
-  // FP32 arithmetic: the pending planes of the paired accumulation (written
-  // by an odd window step before they are read)
+  // FP32 arithmetic: the pending slots of the grouped accumulation (each
+  // written by a window step before it is read)
   if (L->desc.precision != HLBM_FP64 &&
-      (s = lat_alloc(L, (void**)&L->acc_pend,
-                     sizeof(float) * P * (2 + L->dim + (L->desc.track_mean_populations ? L->q : 0)))) != HLBM_OK)
+      (s = lat_alloc(L, (void**)&L->acc_pend, sizeof(float) * pend_slot_elems(L) * (PEND_GROUP - 1))) != HLBM_OK)
     return s;
   if (fresh) {
     HIP_TRY(hipMemsetAsync(L->acc_rho, 0, sizeof(double) * P, L->stream));
@@ -215,16 +214,17 @@ hlbm_status zero_window(hlbm_lattice_s* L) {
   if (L->acc_tau) HIP_TRY(hipMemsetAsync(L->acc_tau, 0, sizeof(double) * P, L->stream));
   if (L->acc_obj) HIP_TRY(hipMemsetAsync(L->acc_obj, 0, sizeof(double) * L->rplane * L->ncoef, L->stream));
   L->nsamp = 0;
-  L->pend_valid = 0;
+  L->pend_n = 0;
   return HLBM_OK;
 }
 
-// Completes the paired accumulation of a run that ended after an odd window
-// step (the sums are whole again outside hlbm_run_primal).
+// Completes the grouped accumulation of a run that ended inside a group (the
+// sums are whole again outside hlbm_run_primal).
 hlbm_status flush_window(hlbm_lattice_s* L) {
-  if (!L->pend_valid) return HLBM_OK;
-  L->pend_valid = 0;
-  HIP_TRY(launch_window_flush(L));
+  if (L->pend_n == 0) return HLBM_OK;
+  const int count = L->pend_n;
+  L->pend_n = 0;
+  HIP_TRY(launch_window_flush(L, count));
   return HLBM_OK;
 }
 
@@ -997,13 +997,14 @@ extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, dou
   // primal: read + write every population once, read d
   const double p = 2.0 * q * ss + ds;
   // window: FP64 read-modify-write of the m dense sums rho, j (+ f, tau) and
-  // the region terms; with the paired accumulation (FP32 arithmetic) one
-  // read-modify-write per pair of steps, the odd step writing m FP32 values
-  // that the even step reads: 12 m per step instead of 16 m
+  // the region terms; with the grouped accumulation (FP32 arithmetic) one
+  // read-modify-write per group of K steps, the first K - 1 writing m FP32
+  // values that the last reads: (16 + 8 (K - 1)) / K per sum and step
   double m = 1.0 + dim;
   if (L->desc.track_mean_populations) m += q;
   if (smag) m += 1.0;
-  double pw = p + (L->desc.precision != HLBM_FP64 ? 12.0 : 16.0) * m;
+  const double K = PEND_GROUP;
+  double pw = p + (L->desc.precision != HLBM_FP64 ? (16.0 + 8.0 * (K - 1.0)) / K : 16.0) * m;
   pw += rfrac * 16.0 * L->ncoef;
   // adjoint: read + write phi, read the frozen coefficients and the source
   const double nsym = dim == 2 ? 3.0 : 6.0;

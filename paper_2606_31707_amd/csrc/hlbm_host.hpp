@@ -11,6 +11,11 @@
 
 namespace hlbm {
 
+// Window steps per FP64 read-modify-write of the dense window sums on FP32
+// and FP16 lattices (the first PEND_GROUP - 1 steps of a group leave their
+// values in FP32 pending slots for the last one).
+constexpr int PEND_GROUP = 4;
+
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Plane stride in elements: a multiple of 256 B, and an odd number of 256 B
@@ -85,8 +90,9 @@ inline const char* footprint_of(const hlbm_desc* desc, int with_window, int with
     b += P * 8 * (1 + dim);
     if (desc->track_mean_populations) b += P * 8 * q;
     if (desc->smagorinsky_cs > 0) b += P * 8;
-    // FP32 pending values of the paired accumulation
-    if (desc->precision != HLBM_FP64) b += P * 4 * (2 + dim + (desc->track_mean_populations ? q : 0));
+    // FP32 pending slots of the grouped accumulation
+    if (desc->precision != HLBM_FP64)
+      b += (uint64_t)(PEND_GROUP - 1) * P * 4 * (2 + dim + (desc->track_mean_populations ? q : 0));
   }
   if (with_adjoint) {
     b += P * as * q;                                    // phi

@@ -9,6 +9,7 @@
 
 #include "../../include/hlbm.h"
 #include "hlbm_device.hpp"
+#include "hlbm_host.hpp"
 
 struct hlbm_lattice_s {
   hlbm_desc desc;
@@ -35,11 +36,12 @@ struct hlbm_lattice_s {
   double* acc_tau = nullptr;  // plane: sum of tau_eff (with the closure)
   double* acc_obj = nullptr;  // ncoef * rplane
   int64_t nsamp = 0;
-  // FP32 and FP16 lattices: (2 + dim [+ q]) FP32 planes of an odd window
-  // step's values, added to the sums by the next even window step (or by a
-  // flush at the end of a run); pend_valid: they are waiting
+  // FP32 and FP16 lattices: PEND_GROUP - 1 slots of (2 + dim [+ q]) FP32
+  // planes holding the values of the first window steps of a group, added
+  // to the sums by the group's last step (or by a flush at the end of a
+  // run); pend_n: slots filled
   float* acc_pend = nullptr;
-  int pend_valid = 0;
+  int pend_n = 0;
 
   // objective region
   int obj_set = 0, obj_kind = 0;
@@ -137,13 +139,18 @@ struct Acc {
   double* f;
   double* tau;
   double* obj;
-  // Paired accumulation (FP32 arithmetic): the pending values of an odd
-  // window step, FP32 planes drho, j (dim), tau_eff, f (q, when tracked);
-  // null where every step adds to the sums at once.  pend_in: this even
-  // window step adds them first.
+  // Grouped accumulation (FP32 arithmetic): the pending values of the
+  // first PEND_GROUP - 1 window steps of a group, PEND_GROUP - 1 slots of
+  // pslot elements, each the FP32 planes drho, j (dim), tau_eff, f (q, when
+  // tracked); null where every step adds to the sums at once.  pend_out:
+  // the slot this step stores its values in (-1: none); pend_in != 0: this
+  // step adds all PEND_GROUP - 1 slots, in slot order, before its own values.
   float* pend = nullptr;
+  int64_t pslot = 0;
+  int pend_out = -1;
   int pend_in = 0;
 };
+
 
 Geo make_geo(const hlbm_lattice_s* L);
 ObjBox make_obj(const hlbm_lattice_s* L);
@@ -152,8 +159,10 @@ dim3 cell_grid(const hlbm_lattice_s* L);
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_init(hlbm_lattice_s* L, double rho0, const double* u_dev);
-// adds the pending values of a last odd window step to the sums
-hipError_t launch_window_flush(hlbm_lattice_s* L);
+// adds the first `count` pending slots of the grouped window accumulation
+// to the sums; elements per pending slot
+hipError_t launch_window_flush(hlbm_lattice_s* L, int count);
+int64_t pend_slot_elems(const hlbm_lattice_s* L);
 hipError_t launch_cylinder(hlbm_lattice_s* L, double xc, double yc, double D,
                            const double* noise_dev, int mode, double box_half, double d_solid);
 hipError_t launch_set_porosity(hlbm_lattice_s* L, const double* d_dev, int* bad_dev);

@@ -776,24 +776,26 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   }
   // Porosity and populations are requested together.
   const T d = (T)at(dpor, c0, lo);
-  // Paired window accumulation (FP32 arithmetic, acc.pend set): an odd
-  // window step stores its values (drho, j, tau_eff, f) as FP32 in the
-  // pending planes instead of adding them to the FP64 sums, and the next
-  // even window step adds them before its own (acc.pend_in): the sums
-  // receive sum + v_odd + v_even, the same FP64 additions in the same order
-  // as when each step adds its value at once (bitwise the same sums), with
-  // one FP64 read-modify-write per pair of steps instead of two.  The
-  // values are FP32 already, so storing them loses nothing.
-  constexpr bool PAIRED = sizeof(T) == 4;
-  const bool pend_out = PAIRED && ODD && ACC != 0 && acc.pend != nullptr;
-  const bool pend_add = PAIRED && !ODD && ACC != 0 && acc.pend_in != 0;
+  // Grouped window accumulation (FP32 arithmetic, acc.pend set): of every
+  // PEND_GROUP consecutive window steps the first PEND_GROUP - 1 store their
+  // values (drho, j, tau_eff, f) as FP32 in a pending slot instead of adding
+  // them to the FP64 sums, and the last adds the pending values in step
+  // order before its own (acc.pend_in): the sums receive
+  // sum + v_1 + ... + v_K, the same FP64 additions in the same order as when
+  // each step adds its value at once (bitwise the same sums), with one FP64
+  // read-modify-write per group instead of one per step.  The values are
+  // FP32 already, so storing them loses nothing.
+  constexpr bool GROUPED = sizeof(T) == 4;
+  constexpr int KP = PEND_GROUP - 1;  // pending slots
+  const bool pend_out = GROUPED && ACC != 0 && acc.pend_out >= 0;
+  const bool pend_add = GROUPED && ACC != 0 && acc.pend_in != 0;
   // Window sums of rho and j: their old values are requested with the
   // populations (and all of them before any is written back, see
   // accumulate_terms).  The inlet's slots are read but not updated.  The
   // dense window sums take their own cache hints (NTW: the populations' in
   // the streaming kernels, and streaming in the D3Q19 odd window step too).
   double wold[L::D + 1];
-  float pold[L::D + 1];
+  float pold[KP][L::D + 1];
   if constexpr (ACC != 0) {
     if (!pend_out) {
       wold[0] = ld_stream<NTW>(&at(acc.rho, c0, lo));
@@ -802,7 +804,10 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
     if (pend_add) {
 #pragma unroll
-      for (int a = 0; a <= L::D; ++a) pold[a] = ld_stream<NTW>(&at(acc.pend, a * g.plane + c0, lo));
+      for (int i = 0; i < KP; ++i)
+#pragma unroll
+        for (int a = 0; a <= L::D; ++a)
+          pold[i][a] = ld_stream<NTW>(&at(acc.pend, i * acc.pslot + a * g.plane + c0, lo));
     }
   }
   // All population loads are issued before any arithmetic on them (the
@@ -889,17 +894,20 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
   (void)oay;
   (void)oaz;
   if (ACC != 0 && !inlet) {  // the pinned inlet is not part of the window
-    // pending planes: drho, j (D), tau_eff, then f (Q)
+    // pending slot planes: drho, j (D), tau_eff, then f (Q)
     constexpr int PT = L::D + 1, PF = L::D + 2;
+    const int64_t sb = pend_out ? (int64_t)acc.pend_out * acc.pslot : 0;
     if (pend_out) {
-      st_stream<NTW>(&at(acc.pend, c0, lo), (float)drho);
-      st_stream<NTW>(&at(acc.pend, g.plane + c0, lo), (float)jx);
-      st_stream<NTW>(&at(acc.pend, 2 * g.plane + c0, lo), (float)jy);
-      if constexpr (L::D == 3) st_stream<NTW>(&at(acc.pend, 3 * g.plane + c0, lo), (float)jz);
+      st_stream<NTW>(&at(acc.pend, sb + c0, lo), (float)drho);
+      st_stream<NTW>(&at(acc.pend, sb + g.plane + c0, lo), (float)jx);
+      st_stream<NTW>(&at(acc.pend, sb + 2 * g.plane + c0, lo), (float)jy);
+      if constexpr (L::D == 3) st_stream<NTW>(&at(acc.pend, sb + 3 * g.plane + c0, lo), (float)jz);
     } else {
       if (pend_add) {
 #pragma unroll
-        for (int a = 0; a <= L::D; ++a) wold[a] = wold[a] + (double)pold[a];
+        for (int i = 0; i < KP; ++i)
+#pragma unroll
+          for (int a = 0; a <= L::D; ++a) wold[a] = wold[a] + (double)pold[i][a];
       }
       st_stream<NTW>(&at(acc.rho, c0, lo), wold[0] + (double)drho);
       st_stream<NTW>(&at(acc.j, c0, lo), wold[1] + (double)jx);
@@ -909,22 +917,27 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     if (acc.f) {  // in groups of 4 (read, then write back)
       if (pend_out) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) st_stream<NTW>(&at(acc.pend, (PF + k) * g.plane + c0, lo), (float)s[k]);
+        for (int k = 0; k < Q; ++k) st_stream<NTW>(&at(acc.pend, sb + (PF + k) * g.plane + c0, lo), (float)s[k]);
       } else {
 #pragma unroll
         for (int k0 = 0; k0 < Q; k0 += 4) {
           double o[4];
-          float po[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
             if (k0 + i < Q) o[i] = ld_stream<NTW>(&at(acc.f, (k0 + i) * g.plane + c0, lo));
           if (pend_add) {
+            float po[KP][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (k0 + i < Q) po[i] = ld_stream<NTW>(&at(acc.pend, (PF + k0 + i) * g.plane + c0, lo));
+            for (int j = 0; j < KP; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (k0 + i < Q) o[i] = o[i] + (double)po[i];
+              for (int i = 0; i < 4; ++i)
+                if (k0 + i < Q)
+                  po[j][i] = ld_stream<NTW>(&at(acc.pend, j * acc.pslot + (PF + k0 + i) * g.plane + c0, lo));
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (k0 + i < Q) o[i] = o[i] + (double)po[j][i];
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -934,10 +947,16 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
     }
     if (acc.tau) {
       if (pend_out) {
-        st_stream<NTW>(&at(acc.pend, PT * g.plane + c0, lo), (float)taue);
+        st_stream<NTW>(&at(acc.pend, sb + PT * g.plane + c0, lo), (float)taue);
       } else {
         double ot = ld_stream<NTW>(&at(acc.tau, c0, lo));
-        if (pend_add) ot = ot + (double)ld_stream<NTW>(&at(acc.pend, PT * g.plane + c0, lo));
+        if (pend_add) {
+          float pt[KP];
+#pragma unroll
+          for (int j = 0; j < KP; ++j) pt[j] = ld_stream<NTW>(&at(acc.pend, j * acc.pslot + PT * g.plane + c0, lo));
+#pragma unroll
+          for (int j = 0; j < KP; ++j) ot = ot + (double)pt[j];
+        }
         st_stream<NTW>(&at(acc.tau, c0, lo), ot + (double)taue);
       }
     }
@@ -1374,23 +1393,26 @@ __global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox
   accumulate_terms<Coef<Q>::N>(acc_obj, ob.rplane, r, terms);
 }
 
-// Completes the paired window accumulation when a run ends after an odd
-// window step: adds the pending FP32 values to the FP64 sums (the same
-// addition the next even window step would have made first).
+// Completes the grouped window accumulation when a run ends inside a group:
+// adds the first `count` pending slots, in slot (step) order, to the FP64
+// sums (the additions the group's last step would have made first).
 template <int Q>
-__global__ __launch_bounds__(256) void k_window_flush(const Geo g, const Acc acc) {
+__global__ __launch_bounds__(256) void k_window_flush(const Geo g, const Acc acc, const int count) {
   using L = Lat<Q>;
   CELL_PROLOGUE
   if (!valid || (inout && x == 0)) return;  // the pinned inlet is not part of the window
-  acc.rho[cell] = acc.rho[cell] + (double)acc.pend[cell];
+  for (int j = 0; j < count; ++j) {
+    const float* pv = acc.pend + j * acc.pslot;
+    acc.rho[cell] = acc.rho[cell] + (double)pv[cell];
 #pragma unroll
-  for (int a = 0; a < L::D; ++a)
-    acc.j[a * g.plane + cell] = acc.j[a * g.plane + cell] + (double)acc.pend[(1 + a) * g.plane + cell];
-  if (acc.tau) acc.tau[cell] = acc.tau[cell] + (double)acc.pend[(L::D + 1) * g.plane + cell];
-  if (acc.f) {
+    for (int a = 0; a < L::D; ++a)
+      acc.j[a * g.plane + cell] = acc.j[a * g.plane + cell] + (double)pv[(1 + a) * g.plane + cell];
+    if (acc.tau) acc.tau[cell] = acc.tau[cell] + (double)pv[(L::D + 1) * g.plane + cell];
+    if (acc.f) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      acc.f[k * g.plane + cell] = acc.f[k * g.plane + cell] + (double)acc.pend[(L::D + 2 + k) * g.plane + cell];
+      for (int k = 0; k < Q; ++k)
+        acc.f[k * g.plane + cell] = acc.f[k * g.plane + cell] + (double)pv[(L::D + 2 + k) * g.plane + cell];
+    }
   }
 }
 

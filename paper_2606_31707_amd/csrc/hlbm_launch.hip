@@ -84,11 +84,16 @@ static void primal_variant(hlbm_lattice_s* L) {
   const ObjBox ob = make_obj(L);
   Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
           c.smag ? L->acc_tau : nullptr, L->acc_obj};
-  if constexpr (ACC != 0) {  // paired window accumulation (FP32 and FP16 lattices)
+  if constexpr (ACC != 0) {  // grouped window accumulation (FP32 and FP16 lattices)
     if (L->acc_pend) {
       acc.pend = L->acc_pend;
-      acc.pend_in = (L->parity == 0 && L->pend_valid) ? 1 : 0;
-      L->pend_valid = L->parity == 1;
+      acc.pslot = pend_slot_elems(L);
+      if (L->pend_n < PEND_GROUP - 1) {  // a group's first steps: store the values
+        acc.pend_out = L->pend_n++;
+      } else {  // its last step: add the stored values, then its own
+        acc.pend_in = 1;
+        L->pend_n = 0;
+      }
     }
   }
   S* A = (S*)L->f;
@@ -179,15 +184,20 @@ hipError_t launch_primal_step(hlbm_lattice_s* L, int accumulate) {
   HLBM_DISPATCH(L, primal_impl, L, accumulate);
 }
 
-hipError_t launch_window_flush(hlbm_lattice_s* L) {
+int64_t pend_slot_elems(const hlbm_lattice_s* L) {
+  return L->plane * (2 + L->dim + (L->desc.track_mean_populations ? L->q : 0));
+}
+
+hipError_t launch_window_flush(hlbm_lattice_s* L, int count) {
   const Geo g = make_geo(L);
   Acc acc{L->acc_rho, L->acc_j, L->desc.track_mean_populations ? L->acc_f : nullptr,
           make_coll(L).smag ? L->acc_tau : nullptr, L->acc_obj};
   acc.pend = L->acc_pend;
+  acc.pslot = pend_slot_elems(L);
   if (L->q == 9)
-    k_window_flush<9><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc);
+    k_window_flush<9><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc, count);
   else
-    k_window_flush<19><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc);
+    k_window_flush<19><<<cell_grid(L), kBlock, 0, L->stream>>>(g, acc, count);
   return hipGetLastError();
 }
 

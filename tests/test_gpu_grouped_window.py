@@ -1,11 +1,13 @@
-"""Paired window accumulation (FP32 and FP16 lattices): an odd window step
-leaves its values (drho, j, tau_eff, f) in FP32 pending planes and the next
-even window step adds them to the FP64 sums before its own, or a flush does
-at the end of a run.  The sums must be bitwise those of launches that add
-every step at once -- the packed group launches, which never pair -- for
-windows that start on either step parity and runs that end on either, with
-the Smagorinsky closure (the tau_eff sum) and the mean populations tracked
-(the f sums, read by the differentiated-closure and HRR adjoints)."""
+"""Grouped window accumulation (FP32 and FP16 lattices): of every four
+consecutive window steps the first three leave their values (drho, j,
+tau_eff, f) in FP32 pending slots and the fourth adds them to the FP64 sums,
+in step order, before its own; a run that ends inside a group is completed by
+a flush.  The sums must be bitwise those of launches that add every step at
+once -- the packed group launches, which never defer -- for windows that
+start on either step parity and runs that end after 3, 2 and 1 pending
+steps, with the Smagorinsky closure (the tau_eff sum) and the mean
+populations tracked (the f sums, read by the differentiated-closure and HRR
+adjoints)."""
 import numpy as np
 import pytest
 
@@ -27,12 +29,12 @@ def _lattice(H, prec, coll):
 
 
 @pytest.mark.parametrize("prec,coll", [(1, 0), (2, 0), (1, 1)])
-def test_paired_sums_equal_unpaired_launches(prec, coll):
+def test_grouped_sums_equal_ungrouped_launches(prec, coll):
     from paper_2606_31707_amd import hlbm as H
-    say("paired window", prec, coll)
+    say("grouped window", prec, coll)
     solo, pack = _lattice(H, prec, coll), _lattice(H, prec, coll)
-    # three plain steps: the window starts on an odd step; the runs end on
-    # odd, even and odd steps
+    # three plain steps: the window starts on an odd step; runs of 7, 10 and
+    # 5 window steps end with 3, 2 and 1 steps pending (groups of four)
     solo.run_primal(3)
     for n in (7, 10, 5):
         solo.run_primal(n, accumulate=True)
@@ -57,13 +59,13 @@ def test_paired_sums_equal_unpaired_launches(prec, coll):
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_window_bytes_per_update(prec):
     """Algorithmic bytes of a window step: 16 B per dense FP64 sum and step
-    (read and write), 12 B with the pairing (a read-modify-write per pair of
-    steps plus one FP32 value written and read)."""
+    (read and write); 10 B with the grouping (a read-modify-write per group
+    of four steps plus three FP32 values written and read)."""
     from paper_2606_31707_amd import hlbm as H
     G = _lattice(H, prec, 0)
     bpu = G.bytes_per_update()
     m = 1 + 3 + 1 + 19  # rho, j, tau_eff, f
     rfrac = 20 * 16 / G.n
-    per_sum = 16.0 if prec == 0 else 12.0
+    per_sum = 16.0 if prec == 0 else (16.0 + 8.0 * 3) / 4
     assert bpu["primal_window"] == pytest.approx(bpu["primal"] + per_sum * m + rfrac * 16.0 * 12, rel=1e-12)
     G.close()
