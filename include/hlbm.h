@@ -260,9 +260,10 @@ hlbm_status hlbm_set_objective(hlbm_lattice lat, int32_t kind, const int32_t lo[
  * once max|u(t) - u(t - check_every)| <= steady_tol max|u|.  *steps_done (may
  * be NULL) receives the steps taken.  Returns DIVERGED on a non-finite check,
  * W_NOT_CONVERGED if steady_tol > 0 was not met.  FP32 and FP16 lattices
- * add the window values of an odd step and the following even step to the
- * FP64 sums in one pass (the same additions in the same order); when the
- * call returns, every step taken is in the sums. */
+ * add the window values of each group of four consecutive steps to the FP64
+ * sums in one pass (the first three steps leave their FP32 values in
+ * pending slots; the same additions in the same order); when the call
+ * returns, every step taken is in the sums. */
 hlbm_status hlbm_run_primal(hlbm_lattice lat, int64_t n_steps, int32_t accumulate,
                             double steady_tol, int64_t check_every, int64_t* steps_done);
 hlbm_status hlbm_window_reset(hlbm_lattice lat);
@@ -335,9 +336,10 @@ hlbm_status hlbm_set_probe(hlbm_lattice lat, int32_t x, int32_t y, int32_t z, in
 hlbm_status hlbm_get_probe(hlbm_lattice lat, double* out, int64_t capacity, int64_t* count);
 /* Algorithmic bytes per lattice update of the primal sweep (accumulate = 0 or
  * 1) and of the adjoint sweep for this lattice's configuration.  A window
- * step of an FP32 or FP16 lattice is counted as the mean over an even/odd
- * pair: its FP64 sums are read and written once per pair, the odd step
- * leaving its values as FP32 for the even step (see hlbm_run_primal). */
+ * step of an FP32 or FP16 lattice is counted as the mean over a group of
+ * four steps: its FP64 sums are read and written once per group, the first
+ * three steps leaving their values as FP32 for the fourth (see
+ * hlbm_run_primal). */
 hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* primal_window,
                                   double* adjoint);
 /* Bandwidth probe (a measurement, not a step of the method): n_launches
