@@ -69,3 +69,57 @@ def test_window_bytes_per_update(prec):
     per_sum = 16.0 if prec == 0 else (16.0 + 8.0 * 3) / 4
     assert bpu["primal_window"] == pytest.approx(bpu["primal"] + per_sum * m + rfrac * 16.0 * 12, rel=1e-12)
     G.close()
+
+
+def test_les_window_means_full_size():
+    """The benchmark lattice (768 x 384 x 128 D3Q19 LES, FP32, the streaming
+    sweeps above the Infinity Cache): a 7-step window run in one call (one
+    group of four, three steps flushed) against the same window run one step
+    per call (every step flushed at once) is bitwise the same, and both are
+    the plain FP64 means of the per-step densities and momenta (host
+    arithmetic on the per-step fields, FP32 rounding of the moments apart)."""
+    from paper_2606_31707_amd import hlbm as H
+    from paper_2606_31707_amd import inputs as I
+    w = I.les_re3900()
+    say("grouped window, full LES lattice")
+
+    def lattice():
+        G = H.Lattice(stencil=w.stencil, precision=H.FP32, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
+                      bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
+                      u_in=w.u_max)
+        G.build_cylinder(w.xc, w.yc, w.D, noise=I.porosity_noise(w), noise_mode=w.noise_mode, box_half=w.box_half)
+        G.init_equilibrium(1.0, I.initial_velocity(w))
+        G.set_objective(w.objective, w.lo, w.hi, u0=w.u0)
+        return G
+
+    W = 7
+    grouped, single = lattice(), lattice()
+    grouped.run_primal(101)  # the window starts on an odd step
+    grouped.run_primal(W, accumulate=True)
+    single.run_primal(101)
+    dr_sum = np.zeros(w.n)
+    j_sum = np.zeros((3, w.n))
+    first = None
+    spread = 0.0
+    for _ in range(W):
+        rho, u = single.field(H.FIELD_RHO), single.field(H.FIELD_U)
+        if first is None:
+            first = rho.copy()
+        spread = max(spread, float(np.abs(rho - first).max()))
+        dr_sum += rho - 1.0
+        j_sum += u * rho
+        single.run_primal(1, accumulate=True)
+    for fld in (H.FIELD_MEAN_RHO, H.FIELD_MEAN_U, H.FIELD_MEAN_TAU):
+        assert np.array_equal(grouped.field(fld), single.field(fld)), fld
+    mean_rho = 1.0 + dr_sum / W
+    mean_u = j_sum / W / mean_rho
+    cols = (np.arange(w.n) % w.nx) > 0  # the pinned inlet is not in the window
+    e_rho = float(np.abs(grouped.field(H.FIELD_MEAN_RHO) - mean_rho)[cols].max())
+    e_u = float(np.abs(grouped.field(H.FIELD_MEAN_U) - mean_u)[:, cols].max())
+    print(f"full-size window: density spread over the window {spread:.2e}, "
+          f"|mean rho - host| {e_rho:.2e}, |mean u - host| {e_u:.2e}", flush=True)
+    # a step dropped or added would move the means by ~spread / W
+    assert spread > 1e-5
+    assert e_rho < 1e-7 and e_u < 1e-7
+    grouped.close()
+    single.close()
