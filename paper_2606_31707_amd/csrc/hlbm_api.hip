@@ -401,7 +401,7 @@ void hlbm_destroy(hlbm_lattice L) {
   (void)hipStreamSynchronize(L->stream);
   void* bufs[] = {L->f,   L->dpor,  L->ghost, L->acc_rho, L->acc_j, L->acc_f, L->acc_tau, L->acc_obj, L->acc_pend,
                   L->phi, L->prep,  L->src,   L->gdat,    L->oprep, L->pv[0], L->pv[1],   L->snap,
-                  L->red, L->usnap, L->probe_buf, L->mea_flag, L->mea_src, L->tan_f, L->tan_ghost,
+                  L->red, L->usnap, L->probe_buf, L->mea_flag, L->mea_src, L->rcopy, L->tan_f, L->tan_ghost,
                   L->tan_v, L->tan_rec};
   for (void* p : bufs) dev_free(p);
   if (L->red_host) (void)hipHostFree(L->red_host);
@@ -562,10 +562,12 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
     lat_free(L, L->src);
     lat_free(L, L->mea_flag);
     lat_free(L, L->mea_src);
+    lat_free(L, L->rcopy);
     L->mea_src = nullptr;
     L->acc_obj = nullptr;
     L->src = nullptr;
     L->mea_flag = nullptr;
+    L->rcopy = nullptr;
     L->rplane = 0;
   }
   hlbm_status s;
@@ -580,6 +582,14 @@ hlbm_status hlbm_set_objective(hlbm_lattice L, int32_t kind, const int32_t lo[3]
     L->mea_src = nullptr;
     if ((s = lat_alloc(L, (void**)&L->mea_flag, L->rplane)) != HLBM_OK) return s;
     if ((s = lat_alloc(L, (void**)&L->mea_src, sizeof(double) * L->q * L->rplane)) != HLBM_OK) return s;
+  }
+  if (region_copy_used((int64_t)rn[0] * rn[1] * rn[2], L->n, kind)) {
+    if ((s = lat_alloc(L, &L->rcopy, L->asize * (size_t)region_copy_stride(L->q, (int)L->asize) * (size_t)L->rplane)) !=
+        HLBM_OK)
+      return s;
+  } else {
+    lat_free(L, L->rcopy);
+    L->rcopy = nullptr;
   }
   L->obj_kind = kind;
   for (int a = 0; a < 3; ++a) {

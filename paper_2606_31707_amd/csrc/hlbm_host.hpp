@@ -18,6 +18,20 @@ constexpr int PEND_GROUP = 4;
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Window steps accumulate the objective terms of a region of at most 1/8 of
+// the lattice in a separate region pass; for the moment-form objectives
+// (not J_MEA, which reads neighbours) the sweep hands that pass each region
+// cell's pre-collision state through a compact copy.
+inline bool region_copy_used(int64_t region_cells, int64_t n, int objective) {
+  return objective != HLBM_OBJ_MEA && region_cells > 0 && region_cells * 8 <= n;
+}
+// Values per region cell in that copy: the q populations and the porosity,
+// padded to whole 128-byte lines (each cell's record fills its own lines, so
+// no line is written by two wavefronts of the sweep).
+constexpr int region_copy_stride(int q, int value_bytes) {
+  return (q + 1 + 128 / value_bytes - 1) / (128 / value_bytes) * (128 / value_bytes);
+}
+
 // Plane stride in elements: a multiple of 256 B, and an odd number of 256 B
 // blocks so that the q planes do not start on the same memory channel (power-
 // of-two strides measured up to 8% slower on the D3Q19 sweeps).
@@ -85,6 +99,8 @@ inline const char* footprint_of(const hlbm_desc* desc, int with_window, int with
     const uint64_t rp = (uint64_t)round_up(region_cells, 128);
     b += 2 * 8 * rp * ncoef;
     if (objective == HLBM_OBJ_MEA) b += rp + 8 * q * rp;  // surface flags and source
+    if (region_copy_used(region_cells, n, objective))  // region cells' state
+      b += rp * (uint64_t)region_copy_stride(q, (int)as) * as;
   }
   if (with_window) {
     b += P * 8 * (1 + dim);

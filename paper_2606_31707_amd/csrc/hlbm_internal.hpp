@@ -48,6 +48,7 @@ struct hlbm_lattice_s {
   int lo[3] = {0, 0, 0}, rn[3] = {1, 1, 1};
   int64_t rplane = 0;
   double u0 = 0.0, p0 = 1.0 / 3.0;
+  void* rcopy = nullptr;              // rplane records: region cells' pre-collision state (region_copy_used)
   unsigned char* mea_flag = nullptr;  // rplane: J_MEA surface nodes of the region
   double* mea_src = nullptr;          // q * rplane: J_MEA's constant dJ/df_k over the region
   int mea_dirty = 1;                  // flags to rebuild (porosity or region changed)
@@ -149,6 +150,11 @@ struct Acc {
   int64_t pslot = 0;
   int pend_out = -1;
   int pend_in = 0;
+  // Window steps with a small moment-form objective region: the sweep
+  // stores each region cell's pre-collision populations and porosity here
+  // (one record of region_copy_stride arithmetic-type values per region
+  // cell, region order) for the region pass that follows it; null otherwise.
+  void* rcopy = nullptr;
 };
 
 

@@ -859,6 +859,26 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
 #pragma unroll
     for (int k = 0; k < Q; ++k) s[k] = (T)0;
   }
+  if constexpr (ACC == 3) {  // a small region's cells hand their state to the region pass
+    int64_t rr;
+    if (acc.rcopy && region_index<Q>(ob, x, y, z, rr)) {
+      // one record of whole 128-byte lines per cell, written as 16-byte vectors
+      constexpr int RC = region_copy_stride(Q, (int)sizeof(T));
+      constexpr int V = 16 / (int)sizeof(T);
+      typedef T TV __attribute__((ext_vector_type(V)));
+      TV* rc = (TV*)((T*)acc.rcopy + rr * RC);
+#pragma unroll
+      for (int v = 0; v < RC / V; ++v) {
+        TV t;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const int k = v * V + i;
+          t[i] = k < Q ? s[k < Q ? k : 0] : (k == Q ? d : (T)0);
+        }
+        rc[v] = t;
+      }
+    }
+  }
 
   T drho, jx, jy, jz;
   cell_moments<Q, T>(s, drho, jx, jy, jz);
@@ -1390,6 +1410,26 @@ __global__ __launch_bounds__(256) void k_window_region(const Geo g, const ObjBox
     neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
     objective_terms<Q>(ob, (double)dpor[cell], dr, ax, ay, az, P, terms);
   }
+  accumulate_terms<Coef<Q>::N>(acc_obj, ob.rplane, r, terms);
+}
+
+// The same objective terms from the copy of the region cells' pre-collision
+// state and porosity that the window sweep wrote (moment-form objectives):
+// one lane per region cell reading its own record, instead of one cache line
+// per population and cell of the lattice.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_window_region_copy(const ObjBox ob, const T* __restrict__ rc,
+                                                            double* __restrict__ acc_obj) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!ob.active || r >= (int64_t)ob.rn[0] * ob.rn[1] * ob.rn[2]) return;
+  const T* rec = rc + r * region_copy_stride(Q, (int)sizeof(T));
+  double sd[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) sd[k] = (double)rec[k];
+  double dr, ax, ay, az, P[6], terms[Coef<Q>::N];
+  cell_moments<Q, double>(sd, dr, ax, ay, az);
+  neq_flux<Q, double>(sd, dr, ax, ay, az, 1.0 / (1.0 + dr), P);
+  objective_terms<Q>(ob, (double)rec[Q], dr, ax, ay, az, P, terms);
   accumulate_terms<Coef<Q>::N>(acc_obj, ob.rplane, r, terms);
 }
 

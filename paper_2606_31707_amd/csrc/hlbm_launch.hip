@@ -96,6 +96,7 @@ static void primal_variant(hlbm_lattice_s* L) {
       }
     }
   }
+  if constexpr (ACC == 3) acc.rcopy = L->obj_kind != HLBM_OBJ_MEA ? L->rcopy : nullptr;
   S* A = (S*)L->f;
   const Dd* dp = (const Dd*)L->dpor;
   S* gh = (S*)L->ghost;
@@ -140,7 +141,13 @@ static void primal_mode(hlbm_lattice_s* L, int accumulate) {
   const int64_t rcells = (int64_t)L->rn[0] * L->rn[1] * L->rn[2];
   if (L->obj_set && rcells * 8 <= L->n) {
     using Dd = typename Prec<S>::Dd;
+    using T = typename Prec<S>::T;
     const dim3 rg((unsigned)((rcells + 255) / 256));  // one lane per region cell
+    if (!mea && L->rcopy) {  // the sweep copies the region cells' state, the pass follows it
+      primal_variant<Q, S, 3, HRR>(L);
+      k_window_region_copy<Q, T><<<rg, 256, 0, L->stream>>>(make_obj(L), (const T*)L->rcopy, L->acc_obj);
+      return;
+    }
     if (mea)
       k_window_region<Q, S, true><<<rg, 256, 0, L->stream>>>(make_geo(L), make_obj(L), (const S*)L->f,
                                                                 (const S*)L->ghost, L->parity,

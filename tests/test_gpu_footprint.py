@@ -18,15 +18,19 @@ def H():
     return hlbm
 
 
-@pytest.mark.parametrize("kind,stencil,prec", [(O.OBJ_DISS, 0, 1), (O.OBJ_MEA, 0, 0), (O.OBJ_DISS, 1, 2)])
+@pytest.mark.parametrize("kind,stencil,prec", [(O.OBJ_DISS, 0, 1), (O.OBJ_MEA, 0, 0), (O.OBJ_DISS, 1, 2),
+                                                (O.OBJ_FFA, 0, 0), (O.OBJ_FFA, 1, 1)])
 def test_device_bytes_equal_the_footprint(kind, stencil, prec):
+    """Large boxes (fused window terms), a J_MEA box, and drag planes (a
+    region pass fed by the sweep's copy of the plane cells' state)."""
     if stencil == 0:
         s = Spec(nx=150, ny=41, tau=0.56, u_in=0.05, cyl=(40.0, 20.0, 10.0))
-        lo, hi = ((2, 0, 0), (140, 40, 0)) if kind == O.OBJ_DISS else ((25, 5, 0), (55, 35, 0))
+        lo, hi = {O.OBJ_DISS: ((2, 0, 0), (140, 40, 0)), O.OBJ_MEA: ((25, 5, 0), (55, 35, 0)),
+                  O.OBJ_FFA: ((100, 0, 0), (100, 40, 0))}[kind]
     else:
         s = Spec(stencil=1, nx=48, ny=20, nz=8, tau=0.55, cs=0.1, bc_y=0, bc_z=0, inlet_profile=1, u_in=0.04,
                  cyl=(14.0, 9.5, 6.0))
-        lo, hi = (2, 0, 0), (40, 19, 7)
+        lo, hi = ((2, 0, 0), (40, 19, 7)) if kind == O.OBJ_DISS else ((36, 0, 0), (36, 19, 7))
     say("footprint", kind, stencil, prec)
     G = make_gpu(s, precision=prec)
     u0 = math.pi * 10.0 if kind == O.OBJ_MEA else 0.05
