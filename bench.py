@@ -443,7 +443,7 @@ def kernel_kind(name: str):
         base, targs = it
     if base in ("k_primal", "k_primal_stream", "k_primal_wstream"):
         return ("primal" if targs[3] == "0" else "primal_window"), targs[2]
-    if base == "k_window_region":
+    if base in ("k_window_region", "k_window_region_copy"):
         return "region", None
     if base == "k_adjoint":
         return "adjoint", targs[2]

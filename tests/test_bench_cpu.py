@@ -28,6 +28,8 @@ def test_kernel_names_map_to_sweep_kinds():
         "void hlbm::k_adjoint_stream<9, double, false, false>(hlbm::Geo)": ("adjoint", "false"),
         "void hlbm::k_adjoint_pstream<19, float, false, false>(hlbm::Geo)": ("adjoint", "true"),
         "void hlbm::k_window_region<19, float, false>(hlbm::Geo)": ("region", None),
+        "void hlbm::k_window_region_copy<19, float>(hlbm::ObjBox, float const*, double*)": ("region", None),
+        "_ZN4hlbm20k_window_region_copyILi9EdEEvNS_6ObjBoxEPKT0_Pd": ("region", None),
         "_ZN4hlbm12k_copy_probeILi19EDF16_Lb1ELb1EEEvNS_3GeoE": ("copy_odd_nt", None),
         "void hlbm::k_copy_probe<9, float, false, false>(hlbm::Geo)": ("copy_own", None),
         "void hlbm::k_gradient<9, double, double>(hlbm::Geo)": (None, None),
