@@ -343,7 +343,8 @@ SWEEP_CASES = {
     "grid2d_fp16s": (I.grid2d_8192x4096, H.FP16S, H.COLL_BGK, False, H.TURB_FROZEN),
 }
 PRECISION_NAMES = {H.FP64: "fp64", H.FP32: "fp32", H.FP16S: "fp16s"}
-PROBES = [("copy_own", 0, False), ("copy_own_nt", 0, True), ("copy_odd", 1, False), ("copy_odd_nt", 1, True)]
+PROBES = [("copy_own", 0, False), ("copy_own_nt", 0, True), ("copy_odd", 1, False), ("copy_odd_nt", 1, True),
+          ("copy_pull", 2, True)]
 
 
 def report_sweeps(case: str, launches: int):
@@ -454,6 +455,8 @@ def kernel_kind(name: str):
     if base == "k_copy_probe":
         odd, nt = targs[2] == "true", targs[3] == "true"
         return ("copy_odd" if odd else "copy_own") + ("_nt" if nt else ""), None
+    if base == "k_copy_probe_pull":
+        return "copy_pull", None
     return None, None
 
 
@@ -606,7 +609,8 @@ def summarize_profiles(d: str):
                  "| counter read MB | counter write MB | traffic / algorithmic | library event us |",
                  "|---|---|---|---|---|---|---|---|---|"]
         bpu = {k: v["bytes_per_update"] for k, v in rep["sweeps"].items()} if rep else {}
-        for kind in ("primal", "primal_window", "adjoint", "copy_own", "copy_own_nt", "copy_odd", "copy_odd_nt"):
+        for kind in ("primal", "primal_window", "adjoint", "copy_own", "copy_own_nt", "copy_odd", "copy_odd_nt",
+                     "copy_pull"):
             us = launch_us(acc, kind)
             if us is None or kind not in bpu:
                 continue
@@ -633,8 +637,9 @@ def summarize_profiles(d: str):
                          + f"{tr} | {ev:.1f} |")
         lines += ["", "`copy_*` rows: the bandwidth probe (`hlbm_copy_probe`), a plain sweep's bytes (populations "
                       "read and written in place, porosity read) with no arithmetic; `_nt` with nontemporal hints; "
-                      "`own` the even step's own slots, `odd` the odd step's upstream slots. The window row includes "
-                      "the region pass of the drag plane.", "", "Kernels (trace):", ""]
+                      "`own` the even step's own slots, `odd` the odd step's upstream slots; `pull` the two-array "
+                      "pattern (upstream slots read, own slots of a second array written with nontemporal hints). "
+                      "The window row includes the region pass of the drag plane.", "", "Kernels (trace):", ""]
         for kind, r in rec.items():
             lines.append(f"- {kind}: " + "; ".join(r["kernels"]))
         traffic["cases"][case] = rec

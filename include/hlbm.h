@@ -348,11 +348,16 @@ hlbm_status hlbm_bytes_per_update(hlbm_lattice lat, double* primal, double* prim
  * cell and writes the populations back unchanged -- on the same workgroups,
  * tile order and addressing, with no arithmetic.  pattern 0: each cell's own
  * slots (the even AA step's accesses); 1: interior cells read and write the
- * odd step's upstream neighbour slots.  streaming != 0: nontemporal hints on
- * every population access.  *us_per_launch receives the mean time per launch
- * (HIP events on the lattice's stream around the launches; synchronises that
- * stream).  The lattice state is unchanged.  Errors: INVALID (pattern,
- * n_launches < 1, null output), DEVICE. */
+ * odd step's upstream neighbour slots; 2: the two-array pull pattern, the
+ * alternative to the in-place propagation -- interior cells read slot i of
+ * their upstream cell x - xi_i and every cell writes its own slots to a
+ * second population array (allocated for the call and freed before it
+ * returns) with nontemporal hints.  streaming != 0: nontemporal hints on
+ * every population access (patterns 0 and 1).  *us_per_launch receives the
+ * mean time per launch (HIP events on the lattice's stream around the
+ * launches; synchronises that stream).  The lattice state is unchanged.
+ * Errors: INVALID (pattern, n_launches < 1, null output), OOM (pattern 2),
+ * DEVICE. */
 hlbm_status hlbm_copy_probe(hlbm_lattice lat, int32_t pattern, int32_t streaming, int64_t n_launches,
                             double* us_per_launch);
 /* Changes the relaxation time, Smagorinsky constant and inflow speed of an

@@ -1037,21 +1037,31 @@ extern "C" hlbm_status hlbm_bytes_per_update(hlbm_lattice L, double* primal, dou
 extern "C" hlbm_status hlbm_copy_probe(hlbm_lattice L, int32_t pattern, int32_t streaming, int64_t n_launches,
                                        double* us_per_launch) {
   CHECK_LAT(L);
-  if (pattern != 0 && pattern != 1) return fail(HLBM_E_INVALID, "pattern must be 0 or 1");
+  if (pattern < 0 || pattern > 2) return fail(HLBM_E_INVALID, "pattern must be 0, 1 or 2");
   if (n_launches < 1 || !us_per_launch) return fail(HLBM_E_INVALID, "need n_launches >= 1 and an output");
+  // pattern 2 writes a second population array, held only for this call
+  void* second = nullptr;
+  if (pattern == 2) {
+    hlbm_status s = dev_alloc(&second, L->ssize * (size_t)L->q * (size_t)L->plane);
+    if (s != HLBM_OK) return s;
+  }
   hipEvent_t ev[2] = {nullptr, nullptr};
-  HIP_TRY(hipEventCreate(&ev[0]));
-  hipError_t e = hipEventCreate(&ev[1]);
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
   if (e == hipSuccess) e = hipEventRecord(ev[0], L->stream);
   // the porosity test that guards the sink is never true (d is in [0, 1])
   for (int64_t k = 0; k < n_launches && e == hipSuccess; ++k)
-    e = launch_copy_probe(L, pattern, streaming != 0, (int*)L->red);
+    e = launch_copy_probe(L, pattern, streaming != 0, (int*)L->red, second);
   if (e == hipSuccess) e = hipEventRecord(ev[1], L->stream);
   if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-  (void)hipEventDestroy(ev[0]);
+  if (ev[0]) (void)hipEventDestroy(ev[0]);
   if (ev[1]) (void)hipEventDestroy(ev[1]);
+  if (second) {
+    (void)hipStreamSynchronize(L->stream);
+    dev_free(second);
+  }
   if (e != hipSuccess) return fail(HLBM_E_DEVICE, "copy probe: %s", hipGetErrorString(e));
   *us_per_launch = 1e3 * (double)ms / (double)n_launches;
   return HLBM_OK;

@@ -189,7 +189,8 @@ hipError_t launch_adjoint_step(hlbm_lattice_s* L);
 hipError_t launch_adjoint_residual(hlbm_lattice_s* L, int first, double* partials, int* nblocks);
 hipError_t launch_gradient(hlbm_lattice_s* L, double* g_dev);
 hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev);
-hipError_t launch_copy_probe(hlbm_lattice_s* L, int pattern, int streaming, int* sink_dev);
+// pattern 2 writes to `second`, an array of the population array's size
+hipError_t launch_copy_probe(hlbm_lattice_s* L, int pattern, int streaming, int* sink_dev, void* second);
 
 // packed launches over groups of lattices
 int tiles_x_of(const hlbm_lattice_s* L);

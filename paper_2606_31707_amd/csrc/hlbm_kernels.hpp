@@ -1190,6 +1190,29 @@ __global__ __launch_bounds__(256) void k_copy_probe(const Geo g, S* __restrict__
   }
 }
 
+// The two-array pull pattern, measured as the alternative to the in-place AA
+// propagation (a probe, not a step of the method): interior cells read slot
+// k of their upstream cell c - xi_k in the lattice's array and write their
+// own slot k of a second array of the same layout with streaming hints;
+// other cells read their own slots.  A plain sweep's bytes again, with twice
+// the population memory.  Same runs and order as the plain step.
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void k_copy_probe_pull(const Geo g, const S* __restrict__ A, S* __restrict__ B,
+                                                         const typename Prec<S>::Dd* __restrict__ dpor,
+                                                         int* __restrict__ sink) {
+  SWEEP_PROLOGUE_RUNS((runs_remap<Q, S, false, 0>()))
+  if (!valid) return;
+  const auto d = at(dpor, tile_c0, tile_lo);
+  const bool nb = interior_cell<Q>(g, x, y, z);
+  S v[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) v[k] = A[k * g.plane + cell - (nb ? nb_offset<Q>(g, k) : 0)];
+  __builtin_amdgcn_sched_barrier(0);
+  if (d < 0) *sink = 1;  // never taken (d is in [0, 1]); keeps the porosity load
+#pragma unroll
+  for (int k = 0; k < Q; ++k) st_stream<true>(&at(B, k * g.plane + tile_c0, tile_lo), v[k]);
+}
+
 // =========================================================================
 // forward tangent (App. C): one primal step of BGK-HLBM together with its
 // directional derivative fdot = (df/dd) v (FP64, no closure).  The tangent

@@ -500,12 +500,14 @@ hipError_t launch_adjoint_gather(hlbm_lattice_s* L, double* out_dev) {
 }
 
 template <int Q, typename S>
-static hipError_t copy_probe_impl(hlbm_lattice_s* L, int pattern, int streaming, int* sink) {
+static hipError_t copy_probe_impl(hlbm_lattice_s* L, int pattern, int streaming, int* sink, void* second) {
   const Geo g = make_geo(L);
   S* A = (S*)L->f;
   const typename Prec<S>::Dd* dp = (const typename Prec<S>::Dd*)L->dpor;
   const dim3 grid = sweep_grid(L);
-  if (pattern == 0) {
+  if (pattern == 2) {
+    k_copy_probe_pull<Q, S><<<grid, kSweepBlock, 0, L->stream>>>(g, A, (S*)second, dp, sink);
+  } else if (pattern == 0) {
     if (streaming)
       k_copy_probe<Q, S, false, true><<<grid, kSweepBlock, 0, L->stream>>>(g, A, dp, sink);
     else
@@ -518,8 +520,8 @@ static hipError_t copy_probe_impl(hlbm_lattice_s* L, int pattern, int streaming,
   }
   return hipGetLastError();
 }
-hipError_t launch_copy_probe(hlbm_lattice_s* L, int pattern, int streaming, int* sink_dev) {
-  HLBM_DISPATCH(L, copy_probe_impl, L, pattern, streaming, sink_dev);
+hipError_t launch_copy_probe(hlbm_lattice_s* L, int pattern, int streaming, int* sink_dev, void* second) {
+  HLBM_DISPATCH(L, copy_probe_impl, L, pattern, streaming, sink_dev, second);
 }
 
 }  // namespace hlbm

@@ -424,7 +424,8 @@ class Lattice:
 
     def copy_probe(self, pattern=0, streaming=False, n_launches=20) -> float:
         """Mean microseconds per launch of the bandwidth probe (a plain sweep's
-        bytes without arithmetic; pattern 0 own slots, 1 odd-step neighbours)."""
+        bytes without arithmetic; pattern 0 own slots, 1 odd-step neighbours,
+        2 the two-array pull pattern)."""
         us = C.c_double()
         _check(self._lib.hlbm_copy_probe(self._h, int(pattern), int(bool(streaming)), int(n_launches),
                                          C.byref(us)))

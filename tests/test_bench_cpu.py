@@ -32,6 +32,7 @@ def test_kernel_names_map_to_sweep_kinds():
         "_ZN4hlbm20k_window_region_copyILi9EdEEvNS_6ObjBoxEPKT0_Pd": ("region", None),
         "_ZN4hlbm12k_copy_probeILi19EDF16_Lb1ELb1EEEvNS_3GeoE": ("copy_odd_nt", None),
         "void hlbm::k_copy_probe<9, float, false, false>(hlbm::Geo)": ("copy_own", None),
+        "void hlbm::k_copy_probe_pull<19, float>(hlbm::Geo, float const*, float*)": ("copy_pull", None),
         "void hlbm::k_gradient<9, double, double>(hlbm::Geo)": (None, None),
         "__amd_rocclr_copyBuffer": (None, None),
     }

@@ -60,8 +60,9 @@ def test_timing_leaves_results_unchanged():
 @pytest.mark.parametrize("stencil,prec", [(0, 0), (0, 2), (1, 1), (1, 2)])
 def test_copy_probe_leaves_the_state_unchanged(stencil, prec):
     """The bandwidth probe reads and writes back every population slot (own
-    slots, or the odd step's neighbour slots): the lattice is bitwise
-    unchanged, in either AA parity, with and without streaming hints."""
+    slots, or the odd step's neighbour slots), or pulls them into a second
+    array it holds for the call: the lattice is bitwise unchanged, in either
+    AA parity, with and without streaming hints, and holds no more memory."""
     say(f"copy probe stencil {stencil} precision {prec}")
     if stencil == 0:
         s = Spec(nx=133, ny=37, tau=0.56, u_in=0.05, cyl=(40.0, 18.0, 10.0))
@@ -76,8 +77,11 @@ def test_copy_probe_leaves_the_state_unchanged(stencil, prec):
             for nt in (False, True):
                 us = G.copy_probe(pattern, nt, 3)
                 assert 0.0 < us < 1e5
+        bytes_held = G.device_bytes()
+        us = G.copy_probe(2, True, 3)  # into a second array of the call's own
+        assert 0.0 < us < 1e5 and G.device_bytes() == bytes_held
         assert np.array_equal(G.populations(), f0)
     with pytest.raises(H().HlbmError):
-        G.copy_probe(2, False, 1)
+        G.copy_probe(3, False, 1)
     with pytest.raises(H().HlbmError):
         G.copy_probe(0, False, 0)
