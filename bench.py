@@ -1228,9 +1228,9 @@ def bench_les(args):
                      "GB_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "launches_timed": prof[k]["sampled"]}
     dom = max(sweeps, key=lambda k: sweeps[k]["ms_per_step"])
     names = {"primal": "k_primal<19, float, *, 0, false> (AA step, Smagorinsky, no window)",
-             "primal_window": "k_window_region<19, float, false> + k_primal(_stream|_wstream)<19, float, *, 3, false> "
-                              "(AA step with the FP64 window: rho, j, tau_eff sums; drag-plane terms by the "
-                              "region pass)",
+             "primal_window": "k_primal(_stream|_wstream)<19, float, *, 3, false> + k_window_region_copy<19, float> "
+                              "(AA step with the FP64 window: rho, j, tau_eff sums updated once per group of four "
+                              "steps; drag-plane terms by the region pass from the sweep's record of the plane)",
              "adjoint": "k_adjoint<19, float, *, false, false> (mean-flow adjoint sweep, frozen turbulence)"}
     d = sweeps[dom]
     khash = kernel_source_hash()
@@ -1270,7 +1270,8 @@ def bench_les(args):
                      "bytes_per_update": d["bytes_per_update"], "updates_per_launch": n,
                      "us_per_launch": d["us_per_launch"],
                      "timing": "HIP events on the sweep stream around blocks of back-to-back launches",
-                     "note": "2.9 GB of FP32 populations and 1.5 GB of FP64 window sums: HBM-resident"},
+                     "note": "2.9 GB of FP32 populations, 1.5 GB of FP64 window sums and 2.3 GB of FP32 pending "
+                             "window values: HBM-resident"},
         "sweeps": sweeps,
     }
     if not args.no_vortex:
