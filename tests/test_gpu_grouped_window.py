@@ -71,20 +71,23 @@ def test_window_bytes_per_update(prec):
     G.close()
 
 
-def test_les_window_means_full_size():
-    """The benchmark lattice (768 x 384 x 128 D3Q19 LES, FP32, the streaming
-    sweeps above the Infinity Cache): a 7-step window run in one call (one
-    group of four, three steps flushed) against the same window run one step
-    per call (every step flushed at once) is bitwise the same, and both are
-    the plain FP64 means of the per-step densities and momenta (host
-    arithmetic on the per-step fields, FP32 rounding of the moments apart)."""
+@pytest.mark.parametrize("prec", [1, 2, 0])
+def test_les_window_means_full_size(prec):
+    """The benchmark lattice (768 x 384 x 128 D3Q19 LES; FP32 and FP16S, and
+    FP64 where every step adds at once; the streaming sweeps above the
+    Infinity Cache): a 7-step window run in one call (one group of four,
+    three steps flushed) against the same window run one step per call
+    (every step flushed at once) is bitwise the same, and both are the plain
+    FP64 means of the per-step densities and momenta (host arithmetic on the
+    per-step fields, the rounding of the moments in the arithmetic type
+    apart)."""
     from paper_2606_31707_amd import hlbm as H
     from paper_2606_31707_amd import inputs as I
     w = I.les_re3900()
-    say("grouped window, full LES lattice")
+    say("grouped window, full LES lattice", prec)
 
     def lattice():
-        G = H.Lattice(stencil=w.stencil, precision=H.FP32, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
+        G = H.Lattice(stencil=w.stencil, precision=prec, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
                       bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
                       u_in=w.u_max)
         G.build_cylinder(w.xc, w.yc, w.D, noise=I.porosity_noise(w), noise_mode=w.noise_mode, box_half=w.box_half)
