@@ -386,7 +386,8 @@ void hlbm_group_destroy(hlbm_group g);
  * per step.  Synchronises every member's own stream.  Members must share
  * stencil, precision and collision model; ADJOINT members need a prepared adjoint
  * (hlbm_solve_adjoint with max_iters = 0).  Until the next hlbm_group_set the
- * members may not be advanced by any other call.  count = 0 empties it. */
+ * members may not be advanced by any other call (hlbm_group_step returns
+ * E_STATE for a member that was).  count = 0 empties it. */
 hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, const int32_t* modes, int32_t count);
 /* Advances every member by n steps / iterations (asynchronous).  On a group
  * with its own stream (not the null stream), a run of n >= 16 steps is

@@ -1104,6 +1104,7 @@ extern "C" void hlbm_group_destroy(hlbm_group g) {
   dev_free(g->first_adjoint);
   delete[] g->members;
   delete[] g->modes;
+  delete[] g->counts0;
   delete g;
 }
 
@@ -1172,11 +1173,14 @@ extern "C" hlbm_status hlbm_group_set(hlbm_group g, const hlbm_lattice* lats, co
   HIP_TRY(hipStreamSynchronize(g->stream));  // host tables go out of scope
   delete[] g->members;
   delete[] g->modes;
+  delete[] g->counts0;
   g->members = count ? new hlbm_lattice_s*[count] : nullptr;
   g->modes = count ? new int32_t[count] : nullptr;
+  g->counts0 = count ? new int64_t[count] : nullptr;
   for (int i = 0; i < count; ++i) {
     g->members[i] = lats[i];
     g->modes[i] = modes[i];
+    g->counts0[i] = modes[i] == HLBM_GROUP_ADJOINT ? lats[i]->adj_iters : lats[i]->steps;
   }
   g->count = count;
   g->n_primal = (int)fp.size();
@@ -1255,6 +1259,15 @@ bool launch_group_graph(hlbm_group_s* g, int64_t n) {
 extern "C" hlbm_status hlbm_group_step(hlbm_group g, int64_t n) {
   if (!g) return fail(HLBM_E_INVALID, "null group");
   if (n < 0) return fail(HLBM_E_INVALID, "negative step count");
+  // the packed tables hold each member's AA parity (or adjoint buffer) as of
+  // the set: a member advanced by any other call since then would be stepped
+  // in the wrong layout
+  for (int i = 0; i < g->count; ++i) {
+    const hlbm_lattice_s* L = g->members[i];
+    const int64_t now = g->modes[i] == HLBM_GROUP_ADJOINT ? L->adj_iters : L->steps;
+    if (now != g->counts0[i] + g->steps_since_set)
+      return fail(HLBM_E_STATE, "member %d was advanced outside the group since hlbm_group_set", i);
+  }
   bool done = false;
   if (n >= kGraphMinSteps && g->stream != nullptr && g->graph_ok) {
     done = launch_group_graph(g, n);

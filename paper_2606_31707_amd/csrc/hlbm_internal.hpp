@@ -225,5 +225,6 @@ struct hlbm_group_s {
   bool graph_ok = true;    // false after a failed capture: plain launches
   hlbm_lattice_s** members = nullptr;
   int32_t* modes = nullptr;
+  int64_t* counts0 = nullptr;  // each member's step (or adjoint iteration) count at the set
   int count = 0;
 };
