@@ -100,3 +100,34 @@ def test_footprint_counts_the_objective_region_without_gpu():
     for bad in [(-1, H.OBJ_DISS), (220 * 41 + 1, H.OBJ_DISS), (10, 7)]:
         with pytest.raises(H.HlbmError):
             H.footprint_bytes(d, True, True, *bad)
+
+
+def test_footprint_counts_pending_window_values_and_the_region_record_without_gpu():
+    """The grouped window accumulation holds three FP32 pending slots of
+    (2 + dim [+ q]) planes on FP32/FP16 lattices (none in FP64); a drag plane
+    (a moment-form region of at most 1/8 of the lattice) holds one record of
+    whole 128-byte lines per region cell for the region pass."""
+    from paper_2606_31707_amd import hlbm as H
+    from paper_2606_31707_amd import inputs as I
+    w = I.les_re3900()
+    for prec, track in ((H.FP64, False), (H.FP32, False), (H.FP16S, False), (H.FP32, True)):
+        d = H.make_desc(stencil=H.D3Q19, precision=prec, nx=w.nx, ny=w.ny, nz=w.nz, tau=w.tau, cs=w.cs,
+                        bc_x=H.BC_INLET_OUTLET, bc_y=w.bc_y, bc_z=w.bc_z, inlet_profile=w.inlet_profile,
+                        u_in=w.u_max, track_mean_populations=track)
+        ssize = {H.FP64: 8, H.FP32: 4, H.FP16S: 2}[prec]
+        unit = 256 // ssize
+        m = -(-w.n // unit)
+        plane = (m + 1 if m % 2 == 0 else m) * unit  # odd number of 256-byte blocks
+        sums = plane * 8 * (1 + 3 + 1 + (19 if track else 0))
+        pending = 0 if prec == H.FP64 else 3 * plane * 4 * (2 + 3 + (19 if track else 0))
+        assert H.footprint_bytes(d, True, False) - H.footprint_bytes(d, False, False) == sums + pending
+        cells = 288 * 128  # the drag plane x = 432, y 48..335
+        rp = -(-cells // 128) * 128
+        asz = 8 if prec == H.FP64 else 4
+        record = -(-20 // (128 // asz)) * (128 // asz)  # 19 populations and d, padded to 128-byte lines
+        ffa = H.footprint_bytes(d, True, False, cells, H.OBJ_FFA) - H.footprint_bytes(d, True, False)
+        assert ffa == 2 * 8 * 12 * rp + rp * record * asz
+        big = w.n // 8 + 1  # above 1/8 of the lattice the terms are fused into the sweep: no record
+        rbig = -(-big // 128) * 128
+        assert H.footprint_bytes(d, True, False, big, H.OBJ_DISS) - H.footprint_bytes(d, True, False) == \
+            2 * 8 * 12 * rbig
