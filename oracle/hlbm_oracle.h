@@ -20,13 +20,13 @@
  *     either differentiated (Sec. 5.4, the dC/df expression with the
  *     (1/tau_eff)^2 term) or frozen (frozen-turbulence assumption, Sec. 5.4).
  *
- * Parity unpinned (in part): the mean-flow gradient of the nonlinear
- * objectives (J_FFA, J_DISS) on a changing flow has no independent ground
- * truth.  Its parts are pinned by the tests (per-cell Jacobians by finite
- * differences, window means as plain means on a changing flow, the whole
- * path against the steady adjoint on a steady flow and, for the linear
- * J_MEA, against the steady path at the mean state); the mean of the
- * nonlinear sources over a changing window is not.
+ * The mean-flow gradient of the nonlinear objectives (J_FFA, J_DISS) on a
+ * changing flow has no closed-form ground truth as a whole; it is pinned by
+ * parts in the tests: per-cell Jacobians by finite differences, window means
+ * as plain means on a changing flow, the window-mean source dJ/df and dJ/dd
+ * by central differences of the per-cell objective at every sampled state,
+ * the whole path against the steady adjoint on a steady flow and, for the
+ * linear J_MEA, against the steady path at the mean state.
  *
  * Conventions: lattice units (dx = dt = 1, c_s^2 = 1/3).  Exchange arrays
  * use the "canonical" layout value[i*n + cell], cell = x + nx*(y + ny*z).
