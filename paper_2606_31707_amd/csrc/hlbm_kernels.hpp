@@ -279,10 +279,12 @@ __device__ __forceinline__ void second_moments(const T (&s)[Q], T (&p)[6]) {
 
 // Non-equilibrium momentum flux with respect to f^eq(rho, u) from the second
 // moments: Pi_ab = p_ab - (drho/3) delta_ab - j_a j_b / rho (same order).
+// drho/3 as a product with the rounded 1/3 (within an ulp of the quotient;
+// an IEEE division is a sequence of about ten instructions per lane).
 template <int Q, typename T>
 __device__ __forceinline__ void neq_from_moments(const T (&p)[6], T drho, T jx, T jy, T jz, T ir, T (&P)[6]) {
   const T pxx = p[0], pyy = p[1], pzz = p[2], pxy = p[3], pxz = p[4], pyz = p[5];
-  const T d3 = drho / (T)3;
+  const T d3 = drho * (T)(1.0 / 3.0);
   P[0] = pxx - d3 - jx * jx * ir;
   P[1] = pyy - d3 - jy * jy * ir;
   P[3] = pxy - jx * jy * ir;
@@ -562,7 +564,8 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
-      a2[a][b] = (a < D && b < D) ? p[pm[a][b]] - (a == b ? drho / (T)3 : (T)0) - rho * ut[a] * ut[b] : (T)0;
+      a2[a][b] = (a < D && b < D) ? p[pm[a][b]] - (a == b ? drho * (T)(1.0 / 3.0) : (T)0) - rho * ut[a] * ut[b]
+                                  : (T)0;
   const T tt = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
   const T tr = a2[0][0] + a2[1][1] + a2[2][2];
   T e3c[H::N], a3[H::N];
@@ -589,7 +592,7 @@ __device__ __forceinline__ void hrr_collide(T (&s)[Q], T drho, T jx, T jy, T jz,
   const T dir = d * ir;
   const T base = drho - (T)1.5 * rho * tt;  // the equilibrium's isotropic part
   const T kn = (T)4.5 * om1;
-  const T base2 = base - kn * (tr / (T)3);   // plus the isotropic part of xi xi : a2
+  const T base2 = base - kn * (tr * (T)(1.0 / 3.0));  // plus the isotropic part of xi xi : a2
   const T ka = (T)3 * rho * dir + om1 * ((T)3 * omd);
   const T kb = (T)4.5 * rho * dir * dir;
   T c3[H::N];
@@ -898,7 +901,7 @@ __device__ __forceinline__ void primal_cell(const Geo& g, const Coll& c, const O
       neq_flux<Q, T>(s, drho, jx, jy, jz, ir, P);
     const T tau0 = (T)c.tau0;
     taue = (T)0.5 * (tau0 + sqrt(tau0 * tau0 + (T)c.kS * sqrt(frob2(P))));
-    omega = (T)1 / taue;
+    omega = recip(taue);  // refined hardware reciprocal, as for 1/rho
   }
 
   // Objective terms of a region cell (moment form): from the pre-collision
